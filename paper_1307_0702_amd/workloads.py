@@ -1,0 +1,270 @@
+"""Seeded synthetic inputs for the inertial-coupling step.
+
+This module only draws and lays out inputs: fluid parameters, particle sets,
+initial fields and forcing descriptions.  It holds none of the step's
+arithmetic and imports nothing from the rest of the package, so the test
+suite can feed the very same arrays to the HIP path and to the CPU oracle.
+
+Grid arrays have shape (nz, ny, nx) (x fastest in memory); particle arrays are
+(N, 3) with columns x, y, z.
+
+Workloads (all synthetic: the paper measures nothing on external data):
+  * "standing-wave-32"  : 32^3, kT = 0, one tethered particle at x = 4 in a
+    modal standing wave of density amplitude 1e-3 (the deterministic Gor'kov
+    case; FP64).
+  * "thermal-128"       : 128^3, kT = 1e-3, 1000 particles, wave 1e-2.
+  * "paper-scale-256"   : 256^3, kT = 1e-3, 10^4 particles, half of each
+    acoustic-contrast sign, wave 1e-2 (the benchmark workload).
+Shared fluid: h = 1, rho0 = 1, c_f = 1, eta = zeta = 0.5, dt = 0.1, V = 8.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Fluid:
+    nx: int
+    ny: int
+    nz: int
+    h: float = 1.0
+    rho0: float = 1.0
+    cf: float = 1.0
+    eta: float = 0.5
+    zeta: float = 0.5
+    kT: float = 0.0
+    dt: float = 0.1
+    seed: int = 0
+    replica: int = 0
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def as_dict(self):
+        return dict(nx=self.nx, ny=self.ny, nz=self.nz, h=self.h, rho0=self.rho0,
+                    cf=self.cf, eta=self.eta, zeta=self.zeta, kT=self.kT, dt=self.dt,
+                    seed=self.seed, replica=self.replica)
+
+
+@dataclass
+class Particles:
+    q: np.ndarray                 # (N, 3) positions
+    me: np.ndarray                # (N,) excess mass m_p - rho0 V
+    kappa_ratio: np.ndarray       # (N,) kappa_p / kappa_f
+    ks: np.ndarray                # (N,) tether spring constants
+    qeq: np.ndarray               # (N, 3) tether anchors
+    fext: np.ndarray = None       # (N, 3) constant external force
+    u: np.ndarray = None          # (N, 3) initial velocity (None: J v)
+
+    def __post_init__(self):
+        n = len(self.q)
+        if self.fext is None:
+            self.fext = np.zeros((n, 3))
+
+    @property
+    def n(self):
+        return len(self.q)
+
+
+@dataclass
+class Mode:
+    """One imposed pressure drive: amp * profile(x_axis) * sin(omega t + phase).
+    shape "cos": profile cos(2 pi m (x - x0)/L); shape "plane": 1 on the plane
+    of cells nearest x0, 0 elsewhere."""
+    axis: int
+    shape: str
+    m: int
+    x0: float
+    amp: float
+    omega: float
+    phase: float = 0.0
+
+    def as_dict(self):
+        return dict(axis=self.axis, shape=self.shape, m=self.m, x0=self.x0,
+                    amp=self.amp, omega=self.omega, phase=self.phase)
+
+
+@dataclass
+class Workload:
+    name: str
+    fluid: Fluid
+    particles: Particles
+    modes: list = field(default_factory=list)
+    drho: np.ndarray = None
+    g: np.ndarray = None           # (3, nz, ny, nx)
+    period_steps: int = 0
+
+
+# ----------------------------------------------------------------------------
+# Field initialisers
+# ----------------------------------------------------------------------------
+
+def random_fields(shape, seed, drho_scale=1e-2, g_scale=1e-2):
+    """Gaussian random density deviation and momentum, for parity tests."""
+    rng = np.random.default_rng(seed)
+    drho = drho_scale * rng.standard_normal(shape)
+    g = g_scale * rng.standard_normal((3,) + tuple(shape))
+    return drho, g
+
+
+def standing_wave_fields(fl: Fluid, amp, axis=0, m=1, x0=0.0, omega=None, t=0.0):
+    """Density and momentum of a linear standing sound wave along `axis`,
+    drho = amp cos(k (x - x0)) cos(omega t) at cell centres and
+    g = amp (omega / k_d) sin(k (x_face - x0)) sin(omega t) on the faces,
+    k = 2 pi m / L and k_d = (2/h) sin(k h / 2) the staggered-grid wavenumber.
+    This is the state a resonantly driven mode settles into, so runs start
+    near it instead of waiting for the transient."""
+    n = (fl.nx, fl.ny, fl.nz)[axis]
+    L = n * fl.h
+    k = 2.0 * math.pi * m / L
+    kd = 2.0 / fl.h * math.sin(k * fl.h / 2.0)
+    if omega is None:
+        omega = fl.cf * kd
+    x = np.arange(n) * fl.h
+    bshape = [1, 1, 1]
+    bshape[2 - axis] = n
+    prof =(amp * np.cos(k * (x - x0)) * math.cos(omega * t)).reshape(bshape)
+    drho = np.broadcast_to(prof, fl.shape).copy()
+    g = np.zeros((3,) + fl.shape)
+    gp = (amp * (omega / kd) * np.sin(k * (x + 0.5 * fl.h - x0)) * math.sin(omega * t)).reshape(bshape)
+    g[axis] = np.broadcast_to(gp, fl.shape)
+    return drho, g
+
+
+def discrete_sound_frequency(fl: Fluid, axis=0, m=1):
+    """omega_d = c_f k_d of mode m along `axis` on the staggered grid."""
+    n = (fl.nx, fl.ny, fl.nz)[axis]
+    k = 2.0 * math.pi * m / (n * fl.h)
+    return fl.cf * 2.0 / fl.h * math.sin(k * fl.h / 2.0)
+
+
+def period_steps(fl: Fluid, omega):
+    """Whole number of steps closest to one drive period."""
+    return int(round(2.0 * math.pi / (omega * fl.dt)))
+
+
+def modal_drive(fl: Fluid, drho_amp, axis=0, m=1, x0=0.0):
+    """A cosine pressure drive whose period is a whole number of steps, with
+    the amplitude P = drho_amp nu_L omega that gives density amplitude
+    drho_amp at resonance (nu_L = (4 eta/3 + zeta)/rho0)."""
+    om_d = discrete_sound_frequency(fl, axis, m)
+    nT = period_steps(fl, om_d)
+    omega = 2.0 * math.pi / (nT * fl.dt)
+    nu_l = (4.0 * fl.eta / 3.0 + fl.zeta) / fl.rho0
+    return Mode(axis=axis, shape="cos", m=m, x0=x0, amp=drho_amp * nu_l * omega,
+                omega=omega), nT
+
+
+# ----------------------------------------------------------------------------
+# Particle sets
+# ----------------------------------------------------------------------------
+
+def uniform_particles(fl: Fluid, n, seed, mass_range=(0.5, 2.0), kappa_range=(0.5, 2.0),
+                      ks=0.0, min_sep=None):
+    """n particles uniform in the box; m_p/(rho0 V) ~ U[mass_range],
+    kappa_p/kappa_f ~ U[kappa_range]; tethered at their start positions with
+    spring constant ks.  If min_sep is given, positions are redrawn until
+    every pair is at least min_sep apart along some axis (periodic), so the
+    kernels do not overlap."""
+    rng = np.random.default_rng(seed)
+    L = np.array([fl.nx, fl.ny, fl.nz]) * fl.h
+    V = 8.0 * fl.h ** 3
+    if min_sep is None:
+        q = rng.random((n, 3)) * L
+    else:
+        pts = []
+        tries = 0
+        while len(pts) < n:
+            tries += 1
+            if tries > 100000:
+                raise RuntimeError("cannot place non-overlapping particles")
+            c = rng.random(3) * L
+            ok = True
+            for p in pts:
+                d = np.abs(c - p)
+                d = np.minimum(d, L - d)
+                if np.all(d < min_sep):
+                    ok = False
+                    break
+            if ok:
+                pts.append(c)
+        q = np.array(pts).reshape(n, 3)
+    mp = rng.uniform(*mass_range, size=n) * fl.rho0 * V
+    kr = rng.uniform(*kappa_range, size=n)
+    return Particles(q=q, me=mp - fl.rho0 * V, kappa_ratio=kr,
+                     ks=np.full(n, float(ks)), qeq=q.copy())
+
+
+def split_contrast_particles(fl: Fluid, n, seed, ks, threshold=0.05):
+    """n particles, half with Gor'kov contrast f1 + 1.5 f2 > threshold and half
+    with < -threshold (f1 = 1 - kappa_p/kappa_f, f2 = 2 m_e/(2 m_e + 3 rho0 V)),
+    drawn as in uniform_particles and rejection-sampled."""
+    rng = np.random.default_rng(seed)
+    L = np.array([fl.nx, fl.ny, fl.nz]) * fl.h
+    V = 8.0 * fl.h ** 3
+    want = n // 2
+    pos, neg = [], []
+    while len(pos) < want or len(neg) < n - want:
+        mp = rng.uniform(0.5, 2.0) * fl.rho0 * V
+        kr = rng.uniform(0.5, 2.0)
+        me = mp - fl.rho0 * V
+        phi_c = (1.0 - kr) + 1.5 * (2.0 * me / (2.0 * me + 3.0 * fl.rho0 * V))
+        if phi_c > threshold and len(pos) < want:
+            pos.append((me, kr))
+        elif phi_c < -threshold and len(neg) < n - want:
+            neg.append((me, kr))
+    props = np.array(pos + neg)
+    q = rng.random((n, 3)) * L
+    return Particles(q=q, me=props[:, 0].copy(), kappa_ratio=props[:, 1].copy(),
+                     ks=np.full(n, float(ks)), qeq=q.copy())
+
+
+# ----------------------------------------------------------------------------
+# Named workloads
+# ----------------------------------------------------------------------------
+
+def standing_wave_32(ks=10.0, x=4.0):
+    """32^3, kT = 0, one particle with m_p = 2 rho0 V and kappa_p = kappa_f/2 at
+    (x, 16, 16), tethered there; cosine drive along x with density amplitude
+    1e-3, whole-step period; fluid starts on the driven standing wave."""
+    fl = Fluid(32, 32, 32, kT=0.0, seed=1)
+    V = 8.0
+    mode, nT = modal_drive(fl, 1e-3)
+    drho, g = standing_wave_fields(fl, 1e-3, omega=mode.omega)
+    q = np.array([[x, 16.0, 16.0]])
+    p = Particles(q=q, me=np.array([2.0 * V - V]), kappa_ratio=np.array([0.5]),
+                  ks=np.array([ks]), qeq=q.copy())
+    return Workload("standing-wave-32", fl, p, [mode], drho, g, nT)
+
+
+def thermal_128(n=1000, seed=2):
+    fl = Fluid(128, 128, 128, kT=1e-3, seed=seed)
+    mode, nT = modal_drive(fl, 1e-2)
+    drho, g = standing_wave_fields(fl, 1e-2, omega=mode.omega)
+    p = uniform_particles(fl, n, seed, ks=10.0)
+    return Workload("thermal-128", fl, p, [mode], drho, g, nT)
+
+
+def paper_scale_256(n=10000, seed=3):
+    fl = Fluid(256, 256, 256, kT=1e-3, seed=seed)
+    mode, nT = modal_drive(fl, 1e-2)
+    drho, g = standing_wave_fields(fl, 1e-2, omega=mode.omega)
+    p = split_contrast_particles(fl, n, seed, ks=10.0)
+    return Workload("paper-scale-256", fl, p, [mode], drho, g, nT)
+
+
+def small_random(nx=20, ny=12, nz=10, npart=6, seed=11, kT=1e-3, min_sep=None):
+    """A small ragged grid with random fields and particles, for parity."""
+    fl = Fluid(nx, ny, nz, kT=kT, seed=seed)
+    drho, g = random_fields(fl.shape, seed)
+    p = uniform_particles(fl, npart, seed + 1, ks=0.3, min_sep=min_sep)
+    rng = np.random.default_rng(seed + 2)
+    p.u = 1e-2 * rng.standard_normal((npart, 3))
+    p.fext = 1e-3 * rng.standard_normal((npart, 3))
+    p.qeq = p.q + rng.uniform(-0.5, 0.5, size=(npart, 3))
+    mode = Mode(axis=0, shape="cos", m=1, x0=1.5, amp=3e-3, omega=0.2, phase=0.3)
+    return Workload("small-random", fl, p, [mode], drho, g, 0)
