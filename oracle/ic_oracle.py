@@ -196,7 +196,10 @@ def cell_normals(seed, step, replica, ncell):
     Philox calls j = 0, 1, 2 use counter (c, step mod 2^32, j, replica) and key
     (seed low 32 bits, seed high 32 bits); word m = 4 j + l of the 12 output
     words gives uniform u_m, and normals (z_2p, z_2p+1) come from Box-Muller
-    of (u_2p, u_2p+1).  Returns (W_A, W_B), each shaped (6, ncell).
+    of (u_2p, u_2p+1).  Reading of the layout: z_0..z_5 are W_A (xx, yy, zz,
+    xy, xz, yz); z_8, z_9, z_10, z_11, z_6, z_7 are W_B (xx, yy, zz, xy, xz,
+    yz), so the last RK stage, which needs W_A only, needs calls 0 and 1.
+    Returns (W_A, W_B), each shaped (6, ncell).
     """
     cid = np.arange(ncell, dtype=np.uint64)
     k0, k1 = int(seed) & 0xFFFFFFFF, (int(seed) >> 32) & 0xFFFFFFFF
@@ -209,7 +212,7 @@ def cell_normals(seed, step, replica, ncell):
         a, b = box_muller(u[2 * p], u[2 * p + 1])
         z += [a, b]
     z = np.array(z)
-    return z[:6], z[6:]
+    return z[:6], z[[8, 9, 10, 11, 6, 7]]
 
 
 def stochastic_stress(Z, prm):
