@@ -1,0 +1,190 @@
+/*
+ * ic.h - C ABI of libic.so: one inertial-coupling (IC) time step of the
+ * compressible, isothermal, fluctuating Navier-Stokes equations on a periodic
+ * staggered grid, coupled to particles through the 3-point kernel, on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: F. Balboa Usabiaga and R. Delgado-Buscalioni, "A minimal model for
+ * acoustic forces on Brownian particles", arXiv:1307.0702.
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns int: IC_OK (0) or a negative IC_E_* code.  Nothing
+ *    throws or aborts across the ABI; ic_last_error() gives a message.
+ *  - Grid arrays hold nx*ny*nz elements, x fastest: cell (i,j,k) is element
+ *    (k*ny + j)*nx + i and sits at r = (i h, j h, k h).  A vector component
+ *    alpha is stored on the alpha-faces: element (i,j,k) of gx sits at
+ *    r + (h/2) e_x (App. A, "Spatial discretization").  The density array
+ *    holds the deviation rho - rho0.
+ *  - Element type of every grid array is float for IC_FP32 and double for
+ *    IC_FP64.  Particle data are always double.
+ *  - "device" pointers point to GPU memory of the current HIP device; "host"
+ *    pointers to CPU memory.  Host inputs are copied before the call returns.
+ *  - Work is enqueued on the HIP stream given to ic_create; device outputs
+ *    are valid once that stream has synchronised.  Calls documented as
+ *    synchronising wait for the stream.
+ *  - A context is not thread-safe; different contexts are independent.
+ */
+#ifndef IC_H
+#define IC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    IC_OK = 0,
+    IC_E_ARG = -1,        /* invalid argument or size */
+    IC_E_UNSTABLE = -2,   /* time step beyond the explicit stability limit */
+    IC_E_MASS = -3,       /* m_p <= 0, c_p^2 < 0, or m_e + m_f <= 0 in a step */
+    IC_E_STATE = -4,      /* call out of order (e.g. step before bind) */
+    IC_E_HIP = -5,        /* a HIP runtime call failed */
+    IC_E_CAPACITY = -6    /* more particles than max_particles */
+};
+
+enum { IC_FP32 = 1, IC_FP64 = 2 };
+
+/* Grid location of a field for ic_interpolate / ic_spread. */
+enum { IC_CELL = 0, IC_FACE_X = 1, IC_FACE_Y = 2, IC_FACE_Z = 3 };
+
+/* Shape of an imposed pressure drive. */
+enum { IC_MODE_COS = 0, IC_MODE_PLANE = 1 };
+
+enum { IC_MAX_MODES = 8 };
+
+/* Fluid and run parameters (Table I of the paper lists its own values).
+ * h grid spacing, rho0 equilibrium density, cf fluid sound speed (pressure
+ * p = p0 + cf^2 rho), eta/zeta shear/bulk viscosity, kT thermal energy
+ * (0 switches the stochastic stress off), dt time step.  seed keys the
+ * Philox generator; replica is its fourth counter word (independent
+ * realisations of one seed).  prec is IC_FP32 or IC_FP64.  max_particles
+ * bounds the particle count of ic_set_particles/ic_interpolate/ic_spread. */
+typedef struct ic_params {
+    int32_t nx, ny, nz;
+    int32_t prec;
+    double h, rho0, cf, eta, zeta, kT, dt;
+    uint64_t seed;
+    uint32_t replica;
+    int32_t max_particles;
+} ic_params;
+
+/* One imposed pressure drive added to the pressure at cell centres:
+ * p_ext = amp * profile(x_axis) * sin(omega t + phase), with
+ *   IC_MODE_COS:   profile = cos(2 pi m (x - x0) / L_axis)
+ *   IC_MODE_PLANE: profile = 1 on the plane of cells nearest x0, else 0
+ *                  (the Kronecker-delta drive of Sec. VI, Eq. pext). */
+typedef struct ic_mode {
+    int32_t axis;   /* 0, 1, 2 = x, y, z */
+    int32_t shape;  /* IC_MODE_COS or IC_MODE_PLANE */
+    int32_t m;      /* mode number for IC_MODE_COS */
+    int32_t pad;
+    double x0, amp, omega, phase;
+} ic_mode;
+
+typedef struct ic_ctx ic_ctx;
+
+/* Validates p and creates a context bound to HIP stream `stream` (NULL =
+ * default stream) on the current device.  Host only; allocates no device
+ * memory.  IC_E_ARG for sizes < 4 per side, non-positive h, rho0, cf, dt,
+ * negative viscosities or kT; IC_E_UNSTABLE when cf dt/h > 0.5 or
+ * (4 eta/3 + zeta)/rho0 * dt/h^2 > 0.2 (reading: the SSP-RK3 stability
+ * region on the imaginary and real axes for the largest staggered-grid
+ * wavenumber; the paper prints no dt rule). */
+int ic_create(const ic_params *p, void *stream, ic_ctx **out);
+
+/* Destroys a context (the caller's buffers are not freed). */
+int ic_destroy(ic_ctx *ctx);
+
+/* Bytes of device workspace a context with parameters p needs. */
+int ic_workspace_size(const ic_params *p, size_t *bytes);
+
+/* Binds caller-owned device buffers: the four state fields (rho - rho0, gx,
+ * gy, gz; each nx*ny*nz elements of the context precision) and a workspace
+ * of at least ic_workspace_size bytes, 256-byte aligned.  The library never
+ * frees them.  Clears the particle set, forcing and averages. */
+int ic_bind(ic_ctx *ctx, void *drho, void *gx, void *gy, void *gz,
+            void *workspace, size_t workspace_bytes);
+
+/* Sets n particles from host arrays (x,y,z triples, i.e. [n][3]):
+ * q positions (wrapped into the box), u velocities or NULL (then u = J v at
+ * q, the no-slip value), me excess masses m_e = m_p - rho0 V with V = 8 h^3
+ * (Sec. IV B, Eq. particleMass), eps particle-fluid energies eps_pf (Sec.
+ * III, Eq. omega), ks tether spring constants or NULL (0), qeq tether anchors
+ * or NULL (= q), fext constant external forces or NULL (0).  IC_E_MASS when
+ * m_e + rho0 V <= 0 or cf^2 + eps < 0 (Eq. part_svel); IC_E_UNSTABLE when
+ * the particle sound speed sqrt(cf^2 + eps) gives c dt/h > 0.5;
+ * IC_E_CAPACITY when n > max_particles.  Resets the force averages.
+ * Synchronising. */
+int ic_set_particles(ic_ctx *ctx, int32_t n, const double *q, const double *u,
+                     const double *me, const double *eps, const double *ks,
+                     const double *qeq, const double *fext);
+
+/* Copies particle positions and velocities ([n][3], host) out; either may be
+ * NULL.  Synchronising. */
+int ic_get_particles(ic_ctx *ctx, double *q, double *u);
+
+/* Sets the imposed pressure drives (nmodes <= IC_MAX_MODES, host array). */
+int ic_set_forcing(ic_ctx *ctx, int32_t nmodes, const ic_mode *modes);
+
+/* Sets / reads the step counter n (time t = n dt; the counter keys the
+ * noise of each step). */
+int ic_set_step(ic_ctx *ctx, int64_t n);
+int ic_get_step(ic_ctx *ctx, int64_t *n);
+
+/* Advances the bound state by nsteps IC time steps (App. A, "Temporal
+ * discretization", substeps 1-7, with the three SSP-RK3 stages of the fluid
+ * update).  Asynchronous.  A step whose no-slip impulse finds m_e + m_f <= 0
+ * raises a device flag reported by the next synchronising call as
+ * IC_E_MASS. */
+int ic_step(ic_ctx *ctx, int64_t nsteps);
+
+/* Averaging operator J (Sec. II, Eq. Jdis; staggered positions of App. A):
+ * out[p] = sum_i h^3 theta_h(q_p - r_i) field[i] for n positions q ([n][3],
+ * device) and a field of the given location kind (device, context
+ * precision, nx*ny*nz).  out is device, double[n].  Asynchronous. */
+int ic_interpolate(ic_ctx *ctx, int32_t n, const double *q, int32_t kind,
+                   const void *field, double *out);
+
+/* Spreading operator S (Sec. II, Eq. Sdis): adds theta_h(q_p - r_i) f[p] to
+ * field[i] for every p, so sum_i h^3 field[i] grows by sum_p f[p].  q
+ * ([n][3]) and f (double[n]) are device arrays; field is device (context
+ * precision).  Deterministic (no float atomics).  Asynchronous; uses the
+ * context workspace, so it must not overlap an ic_step of the context. */
+int ic_spread(ic_ctx *ctx, int32_t n, const double *q, const double *f, int32_t kind,
+              void *field);
+
+/* Window averages since the last reset, per particle ([n][3], host, either
+ * may be NULL): the mean of -F_tether = k_s minimg(q^{n+1/2} - q_eq), the
+ * spring-force estimator of the radiation force (Sec. VI), and the mean of
+ * the fluid force lambda = m_e (u^{n+1} - u^n)/dt - F^{n+1/2} (Sec. IV B,
+ * Eq. partVel).  *nsamples gets the number of steps averaged.  reset != 0
+ * starts a new window.  Synchronising. */
+int ic_avg_force(ic_ctx *ctx, double *f_out, double *lambda_out, int64_t *nsamples,
+                 int32_t reset);
+
+/* FP64 sums of the bound state: out[0] = sum h^3 (rho - rho0), out[1..3] =
+ * sum h^3 g + sum_p m_e u_p (Sec. IV C, total momentum).  Synchronising. */
+int ic_conserved(ic_ctx *ctx, double out[4]);
+
+/* Instrumentation.  With enable != 0, ic_step brackets every fluid-stage
+ * kernel launch (the three RK sweeps of App. A) with HIP events on the
+ * context stream.  ic_profile_read synchronises, returns the summed duration
+ * of those kernels in ms and their number of launches since the last read,
+ * and clears both. */
+int ic_profile(ic_ctx *ctx, int32_t enable);
+int ic_profile_read(ic_ctx *ctx, double *stage_ms, int64_t *launches);
+
+/* eps_pf from kappa_p/kappa_f: cf^2 (kappa_f/kappa_p - 1) (Sec. III, Eqs.
+ * part_svel and ke). */
+double ic_eps_from_kappa_ratio(double cf, double kappa_ratio);
+
+const char *ic_strerror(int code);
+const char *ic_last_error(const ic_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IC_H */

@@ -1,0 +1,479 @@
+// C ABI of libic.so (declared and documented in include/ic.h): argument
+// checks, workspace layout, host<->device copies and the per-call launch
+// sequence.  All device work is in ic_device.hip.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "ic_internal.h"
+
+namespace ic {
+
+namespace {
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int tiles(int n, int t) { return (n + t - 1) / t; }
+
+}  // namespace
+
+int nblocks_total(const ic_params &p) {
+    return tiles(p.nx, TX) * tiles(p.ny, TY) * tiles(p.nz, TZ);
+}
+
+// Walks the workspace layout; with base == nullptr it only measures.
+static size_t layout(const ic_params &p, char *base, Workspace *ws) {
+    const size_t ncell = (size_t)p.nx * p.ny * p.nz;
+    const size_t esz = p.prec == IC_FP64 ? 8 : 4;
+    const size_t N = p.max_particles > 0 ? (size_t)p.max_particles : 1;
+    const size_t nblk = (size_t)nblocks_total(p);
+    const int pmax = p.nx > p.ny ? (p.nx > p.nz ? p.nx : p.nz) : (p.ny > p.nz ? p.ny : p.nz);
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *ptr = base ? base + off : nullptr;
+        off = align_up(off + bytes);
+        return ptr;
+    };
+    Workspace w{};
+    for (int i = 0; i < 4; ++i) w.A[i] = take(ncell * esz);
+    for (int i = 0; i < 4; ++i) w.B[i] = take(ncell * esz);
+    auto d3 = [&]() { return (double *)take(3 * N * sizeof(double)); };
+    auto d1 = [&]() { return (double *)take(N * sizeof(double)); };
+    w.q = d3(); w.u = d3(); w.me = d1(); w.eps = d1(); w.ks = d1(); w.qeq = d3(); w.fext = d3();
+    w.qh = d3(); w.jv_old = d3(); w.F = d3(); w.Vt = d3(); w.du = d3(); w.mf = d3();
+    w.omega = d1(); w.jv_new = d3();
+    w.pk.bc = (int32_t *)take(3 * N * sizeof(int32_t));
+    w.pk.bf = (int32_t *)take(3 * N * sizeof(int32_t));
+    w.pk.wc = (double *)take(9 * N * sizeof(double));
+    w.pk.wf = (double *)take(9 * N * sizeof(double));
+    w.blk_count = (int32_t *)take((nblk + 1) * sizeof(int32_t));
+    w.blk_off = (int32_t *)take((nblk + 1) * sizeof(int32_t));
+    w.blk_cursor = (int32_t *)take((nblk + 1) * sizeof(int32_t));
+    w.blk_list = (int32_t *)take(N * MAX_BLOCKS_PER_PARTICLE * sizeof(int32_t));
+    w.sum_f = d3(); w.sum_l = d3();
+    w.prof = (double *)take((size_t)IC_MAX_MODES * pmax * sizeof(double));
+    w.red = (double *)take(4 * 1024 * sizeof(double));
+    w.flag = (int32_t *)take(sizeof(int32_t) * 4);
+    if (ws) *ws = w;
+    return off;
+}
+
+size_t workspace_bytes(const ic_params &p, size_t *) { return layout(p, nullptr, nullptr); }
+
+void carve_workspace(const ic_params &p, char *base, Workspace &ws) { layout(p, base, &ws); }
+
+hipEvent_t prof_event(ic_ctx *c) {
+    if (!c->profiling) return nullptr;
+    if (c->ev_pool.empty()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+}
+
+void prof_push(ic_ctx *c, hipEvent_t a, hipEvent_t b) {
+    if (a && b)
+        c->ev_pending.emplace_back(a, b);
+    else {
+        if (a) c->ev_pool.push_back(a);
+        if (b) c->ev_pool.push_back(b);
+    }
+}
+
+}  // namespace ic
+
+using namespace ic;
+
+namespace {
+
+int fail(ic_ctx *c, int code, const char *msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(ic_ctx *c, hipError_t e, const char *where) {
+    if (c) {
+        c->err = std::string(where) + ": " + hipGetErrorString(e);
+    }
+    return IC_E_HIP;
+}
+
+int check_params(const ic_params *p, ic_ctx *c) {
+    if (!p) return fail(c, IC_E_ARG, "params is NULL");
+    if (p->nx < 4 || p->ny < 4 || p->nz < 4)
+        return fail(c, IC_E_ARG, "grid must have at least 4 cells per side");
+    if ((double)p->nx * p->ny * p->nz > 2147483647.0)
+        return fail(c, IC_E_ARG, "grid larger than 2^31 cells");
+    if (p->prec != IC_FP32 && p->prec != IC_FP64) return fail(c, IC_E_ARG, "prec must be IC_FP32 or IC_FP64");
+    if (!(p->h > 0) || !(p->rho0 > 0) || !(p->cf > 0) || !(p->dt > 0))
+        return fail(c, IC_E_ARG, "h, rho0, cf and dt must be positive");
+    if (!(p->eta >= 0) || !(p->zeta >= 0) || !(p->kT >= 0))
+        return fail(c, IC_E_ARG, "eta, zeta and kT must be non-negative");
+    if (!isfinite(p->h + p->rho0 + p->cf + p->dt + p->eta + p->zeta + p->kT))
+        return fail(c, IC_E_ARG, "parameters must be finite");
+    if (p->max_particles < 0) return fail(c, IC_E_ARG, "max_particles must be >= 0");
+    if (p->cf * p->dt / p->h > 0.5) return fail(c, IC_E_UNSTABLE, "cf dt / h > 0.5");
+    const double nu_l = (4.0 * p->eta / 3.0 + p->zeta) / p->rho0;
+    if (nu_l * p->dt / (p->h * p->h) > 0.2)
+        return fail(c, IC_E_UNSTABLE, "(4 eta/3 + zeta)/rho0 dt/h^2 > 0.2");
+    return IC_OK;
+}
+
+int check_bound(ic_ctx *c) {
+    if (!c) return IC_E_ARG;
+    if (!c->bound) return fail(c, IC_E_STATE, "fields and workspace are not bound");
+    return IC_OK;
+}
+
+int take_flag(ic_ctx *c) {
+    int32_t flag = 0;
+    hipError_t e = hipMemcpyAsync(&flag, c->ws.flag, sizeof(flag), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "flag readback");
+    if (flag) {
+        int32_t zero = 0;
+        e = hipMemcpyAsync(c->ws.flag, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "flag reset");
+        return fail(c, IC_E_MASS, "a step found m_e + m_f <= 0");
+    }
+    return IC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ic_create(const ic_params *p, void *stream, ic_ctx **out) {
+    if (!out) return IC_E_ARG;
+    *out = nullptr;
+    const int rc = check_params(p, nullptr);
+    if (rc != IC_OK) return rc;
+    ic_ctx *c = new (std::nothrow) ic_ctx();
+    if (!c) return IC_E_ARG;
+    c->p = *p;
+    c->stream = (hipStream_t)stream;
+    c->device = 0;
+    (void)hipGetDevice(&c->device);
+    c->bound = false;
+    c->np = 0;
+    c->step = 0;
+    c->nsamples = 0;
+    c->forcing.nmodes = 0;
+    c->nblk[0] = (p->nx + TX - 1) / TX;
+    c->nblk[1] = (p->ny + TY - 1) / TY;
+    c->nblk[2] = (p->nz + TZ - 1) / TZ;
+    int pmax = p->nx > p->ny ? p->nx : p->ny;
+    if (p->nz > pmax) pmax = p->nz;
+    c->prof_stride = pmax;
+    c->profiling = false;
+    c->prof_ms = 0.0;
+    c->prof_launches = 0;
+    *out = c;
+    return IC_OK;
+}
+
+int ic_destroy(ic_ctx *c) {
+    if (!c) return IC_OK;
+    if (!c->ev_pending.empty()) (void)hipStreamSynchronize(c->stream);
+    for (auto &pr : c->ev_pending) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+    return IC_OK;
+}
+
+int ic_profile(ic_ctx *c, int32_t enable) {
+    if (!c) return IC_E_ARG;
+    c->profiling = enable != 0;
+    return IC_OK;
+}
+
+int ic_profile_read(ic_ctx *c, double *stage_ms, int64_t *launches) {
+    if (!c) return IC_E_ARG;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "profile sync");
+    for (auto &pr : c->ev_pending) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, pr.first, pr.second);
+        if (e != hipSuccess) return hip_fail(c, e, "profile elapsed");
+        c->prof_ms += ms;
+        c->prof_launches += 1;
+        c->ev_pool.push_back(pr.first);
+        c->ev_pool.push_back(pr.second);
+    }
+    c->ev_pending.clear();
+    if (stage_ms) *stage_ms = c->prof_ms;
+    if (launches) *launches = c->prof_launches;
+    c->prof_ms = 0.0;
+    c->prof_launches = 0;
+    return IC_OK;
+}
+
+int ic_workspace_size(const ic_params *p, size_t *bytes) {
+    if (!bytes) return IC_E_ARG;
+    const int rc = check_params(p, nullptr);
+    if (rc != IC_OK) return rc;
+    *bytes = workspace_bytes(*p);
+    return IC_OK;
+}
+
+int ic_bind(ic_ctx *c, void *drho, void *gx, void *gy, void *gz, void *workspace,
+            size_t workspace_bytes_) {
+    if (!c) return IC_E_ARG;
+    if (!drho || !gx || !gy || !gz || !workspace) return fail(c, IC_E_ARG, "NULL buffer");
+    if (((uintptr_t)workspace & 255) != 0) return fail(c, IC_E_ARG, "workspace not 256-byte aligned");
+    if (workspace_bytes_ < workspace_bytes(c->p)) return fail(c, IC_E_ARG, "workspace too small");
+    c->f[0] = drho;
+    c->f[1] = gx;
+    c->f[2] = gy;
+    c->f[3] = gz;
+    carve_workspace(c->p, (char *)workspace, c->ws);
+    c->np = 0;
+    c->nsamples = 0;
+    c->forcing.nmodes = 0;
+    hipError_t e = hipMemsetAsync(c->ws.flag, 0, 4 * sizeof(int32_t), c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "bind");
+    c->bound = true;
+    return IC_OK;
+}
+
+int ic_set_particles(ic_ctx *c, int32_t n, const double *q, const double *u, const double *me,
+                     const double *eps, const double *ks, const double *qeq, const double *fext) {
+    int rc = check_bound(c);
+    if (rc != IC_OK) return rc;
+    if (n < 0) return fail(c, IC_E_ARG, "n < 0");
+    if (n > c->p.max_particles) return fail(c, IC_E_CAPACITY, "n > max_particles");
+    if (n > 0 && (!q || !me || !eps)) return fail(c, IC_E_ARG, "q, me and eps are required");
+    const ic_params &p = c->p;
+    const double V = 8.0 * p.h * p.h * p.h;
+    const double L[3] = {p.nx * p.h, p.ny * p.h, p.nz * p.h};
+    double max_eps = 0.0;
+    for (int i = 0; i < n; ++i) {
+        for (int a = 0; a < 3; ++a)
+            if (!isfinite(q[3 * i + a])) return fail(c, IC_E_ARG, "non-finite position");
+        if (!isfinite(me[i]) || !isfinite(eps[i])) return fail(c, IC_E_ARG, "non-finite particle property");
+        if (!(me[i] + p.rho0 * V > 0.0)) return fail(c, IC_E_MASS, "particle mass m_e + rho0 V <= 0");
+        if (!(p.cf * p.cf + eps[i] >= 0.0)) return fail(c, IC_E_MASS, "c_p^2 = cf^2 + eps < 0");
+        if (eps[i] > max_eps) max_eps = eps[i];
+    }
+    if (sqrt(p.cf * p.cf + max_eps) * p.dt / p.h > 0.5)
+        return fail(c, IC_E_UNSTABLE, "particle sound speed gives c dt / h > 0.5");
+    std::vector<double> hq(3 * (size_t)n), hzero(3 * (size_t)n, 0.0), hks((size_t)n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            double x = fmod(q[3 * i + a], L[a]);
+            if (x < 0) x += L[a];
+            if (x >= L[a]) x -= L[a];
+            hq[3 * i + a] = x;
+        }
+    if (ks)
+        for (int i = 0; i < n; ++i) hks[i] = ks[i];
+    const Workspace &w = c->ws;
+    const size_t b3 = 3 * (size_t)n * sizeof(double), b1 = (size_t)n * sizeof(double);
+    hipError_t e = hipSuccess;
+    auto cp = [&](void *dst, const void *src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream);
+    };
+    cp(w.q, hq.data(), b3);
+    cp(w.me, me, b1);
+    cp(w.eps, eps, b1);
+    cp(w.ks, hks.data(), b1);
+    cp(w.qeq, qeq ? qeq : hq.data(), b3);
+    cp(w.fext, fext ? fext : hzero.data(), b3);
+    cp(w.sum_f, hzero.data(), b3);
+    cp(w.sum_l, hzero.data(), b3);
+    if (u) cp(w.u, u, b3);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "set_particles copy");
+    c->np = n;
+    c->nsamples = 0;
+    if (!u && n > 0) {
+        e = launch_init_velocity(c);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "initial velocity");
+    }
+    return IC_OK;
+}
+
+int ic_get_particles(ic_ctx *c, double *q, double *u) {
+    int rc = check_bound(c);
+    if (rc != IC_OK) return rc;
+    const size_t b3 = 3 * (size_t)c->np * sizeof(double);
+    hipError_t e = hipSuccess;
+    if (q && b3) e = hipMemcpyAsync(q, c->ws.q, b3, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && u && b3) e = hipMemcpyAsync(u, c->ws.u, b3, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "get_particles");
+    return take_flag(c);
+}
+
+int ic_set_forcing(ic_ctx *c, int32_t nmodes, const ic_mode *modes) {
+    int rc = check_bound(c);
+    if (rc != IC_OK) return rc;
+    if (nmodes < 0 || nmodes > IC_MAX_MODES) return fail(c, IC_E_ARG, "nmodes out of range");
+    if (nmodes > 0 && !modes) return fail(c, IC_E_ARG, "modes is NULL");
+    const ic_params &p = c->p;
+    const int n_of[3] = {p.nx, p.ny, p.nz};
+    std::vector<double> prof((size_t)IC_MAX_MODES * c->prof_stride, 0.0);
+    for (int m = 0; m < nmodes; ++m) {
+        const ic_mode &md = modes[m];
+        if (md.axis < 0 || md.axis > 2) return fail(c, IC_E_ARG, "mode axis must be 0, 1 or 2");
+        if (md.shape != IC_MODE_COS && md.shape != IC_MODE_PLANE) return fail(c, IC_E_ARG, "bad mode shape");
+        if (!isfinite(md.x0 + md.amp + md.omega + md.phase)) return fail(c, IC_E_ARG, "non-finite mode");
+        const int n = n_of[md.axis];
+        double *pr = prof.data() + (size_t)m * c->prof_stride;
+        if (md.shape == IC_MODE_PLANE) {
+            long i0 = (long)floor(md.x0 / p.h + 0.5);
+            i0 %= n;
+            if (i0 < 0) i0 += n;
+            pr[i0] = 1.0;
+        } else {
+            const double L = n * p.h;
+            for (int i = 0; i < n; ++i) pr[i] = cos(2.0 * M_PI * md.m * (i * p.h - md.x0) / L);
+        }
+        c->forcing.modes[m] = md;
+    }
+    hipError_t e = hipMemcpyAsync(c->ws.prof, prof.data(), prof.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "set_forcing");
+    c->forcing.nmodes = nmodes;
+    return IC_OK;
+}
+
+int ic_set_step(ic_ctx *c, int64_t n) {
+    if (!c) return IC_E_ARG;
+    if (n < 0) return fail(c, IC_E_ARG, "step must be >= 0");
+    c->step = n;
+    return IC_OK;
+}
+
+int ic_get_step(ic_ctx *c, int64_t *n) {
+    if (!c || !n) return IC_E_ARG;
+    *n = c->step;
+    return IC_OK;
+}
+
+int ic_step(ic_ctx *c, int64_t nsteps) {
+    int rc = check_bound(c);
+    if (rc != IC_OK) return rc;
+    if (nsteps < 0) return fail(c, IC_E_ARG, "nsteps < 0");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        hipError_t e = launch_step(c);
+        if (e != hipSuccess) return hip_fail(c, e, "step launch");
+        c->step += 1;
+        if (c->np > 0) c->nsamples += 1;
+    }
+    return IC_OK;
+}
+
+int ic_interpolate(ic_ctx *c, int32_t n, const double *q, int32_t kind, const void *field,
+                   double *out) {
+    if (!c) return IC_E_ARG;
+    if (n < 0) return fail(c, IC_E_ARG, "n < 0");
+    if (kind < IC_CELL || kind > IC_FACE_Z) return fail(c, IC_E_ARG, "bad kind");
+    if (n == 0) return IC_OK;
+    if (!q || !field || !out) return fail(c, IC_E_ARG, "NULL pointer");
+    hipError_t e = launch_interpolate(c, n, q, kind, field, out);
+    if (e != hipSuccess) return hip_fail(c, e, "interpolate launch");
+    return IC_OK;
+}
+
+int ic_spread(ic_ctx *c, int32_t n, const double *q, const double *f, int32_t kind, void *field) {
+    int rc = check_bound(c);
+    if (rc != IC_OK) return rc;
+    if (n < 0) return fail(c, IC_E_ARG, "n < 0");
+    if (n > c->p.max_particles) return fail(c, IC_E_CAPACITY, "n > max_particles");
+    if (kind < IC_CELL || kind > IC_FACE_Z) return fail(c, IC_E_ARG, "bad kind");
+    if (n == 0) return IC_OK;
+    if (!q || !f || !field) return fail(c, IC_E_ARG, "NULL pointer");
+    hipError_t e = launch_spread(c, n, q, f, kind, field);
+    if (e != hipSuccess) return hip_fail(c, e, "spread launch");
+    return IC_OK;
+}
+
+int ic_avg_force(ic_ctx *c, double *f_out, double *lambda_out, int64_t *nsamples, int32_t reset) {
+    int rc = check_bound(c);
+    if (rc != IC_OK) return rc;
+    const size_t n3 = 3 * (size_t)c->np;
+    std::vector<double> sf(n3), sl(n3);
+    hipError_t e = hipSuccess;
+    if (n3) {
+        e = hipMemcpyAsync(sf.data(), c->ws.sum_f, n3 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(sl.data(), c->ws.sum_l, n3 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "avg_force readback");
+    const double inv = c->nsamples > 0 ? 1.0 / (double)c->nsamples : 0.0;
+    for (size_t i = 0; i < n3; ++i) {
+        if (f_out) f_out[i] = sf[i] * inv;
+        if (lambda_out) lambda_out[i] = sl[i] * inv;
+    }
+    if (nsamples) *nsamples = c->nsamples;
+    if (reset) {
+        std::vector<double> z(n3, 0.0);
+        if (n3) {
+            e = hipMemcpyAsync(c->ws.sum_f, z.data(), n3 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(c->ws.sum_l, z.data(), n3 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "avg_force reset");
+        }
+        c->nsamples = 0;
+    }
+    return take_flag(c);
+}
+
+int ic_conserved(ic_ctx *c, double out[4]) {
+    int rc = check_bound(c);
+    if (rc != IC_OK) return rc;
+    if (!out) return fail(c, IC_E_ARG, "out is NULL");
+    double s[4];
+    hipError_t e = launch_conserved(c, s);
+    if (e != hipSuccess) return hip_fail(c, e, "conserved");
+    const double h3 = c->p.h * c->p.h * c->p.h;
+    for (int k = 0; k < 4; ++k) out[k] = h3 * s[k];
+    if (c->np > 0) {
+        const size_t n = (size_t)c->np;
+        std::vector<double> u(3 * n), me(n);
+        e = hipMemcpyAsync(u.data(), c->ws.u, 3 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(me.data(), c->ws.me, n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "conserved particles");
+        for (size_t i = 0; i < n; ++i)
+            for (int a = 0; a < 3; ++a) out[1 + a] += me[i] * u[3 * i + a];
+    }
+    return take_flag(c);
+}
+
+double ic_eps_from_kappa_ratio(double cf, double kappa_ratio) {
+    return cf * cf * (1.0 / kappa_ratio - 1.0);
+}
+
+const char *ic_strerror(int code) {
+    switch (code) {
+        case IC_OK: return "ok";
+        case IC_E_ARG: return "invalid argument";
+        case IC_E_UNSTABLE: return "time step beyond the stability limit";
+        case IC_E_MASS: return "non-positive mass or negative squared sound speed";
+        case IC_E_STATE: return "call out of order";
+        case IC_E_HIP: return "HIP runtime error";
+        case IC_E_CAPACITY: return "too many particles";
+        default: return "unknown error";
+    }
+}
+
+const char *ic_last_error(const ic_ctx *c) { return c ? c->err.c_str() : "no context"; }
+
+}  // extern "C"

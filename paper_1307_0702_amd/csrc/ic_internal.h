@@ -1,0 +1,103 @@
+// Internal declarations shared by the C-ABI layer and the HIP kernels of
+// libic.so.  Not part of the public interface (include/ic.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "ic.h"
+
+namespace ic {
+
+// Stage-kernel tile: TX cells along x (one half-wave row each), TY rows along
+// y, marching over up to TZ planes along z.  One thread per (x, y) column.
+constexpr int TX = 32;
+constexpr int TY = 8;
+constexpr int TZ = 32;
+constexpr int STAGE_THREADS = TX * TY;
+// Largest number of stencil blocks one particle's influence box can touch
+// (at most 3 tiles per axis).
+constexpr int MAX_BLOCKS_PER_PARTICLE = 27;
+
+// Per-particle kernel data at q^{n+1/2}, fixed during the three RK stages
+// (App. A, substep 3): first index of the 3 cell-centred and of the 3
+// face-shifted kernel points along each axis, and their weights phi.
+struct PartKernel {
+    int32_t *bc;     // [N][3] first cell index of the cell stencil
+    int32_t *bf;     // [N][3] first face index of the face stencil
+    double *wc;      // [N][3][3] phi at the cell points, per axis
+    double *wf;      // [N][3][3] phi at the face points, per axis
+};
+
+// Device workspace carved out of the caller's buffer.
+struct Workspace {
+    void *A[4];          // stage buffer U~ (drho, gx, gy, gz)
+    void *B[4];          // stage buffer U^{n+1/2}
+    // persistent particle state, [N][3] or [N]
+    double *q, *u, *me, *eps, *ks, *qeq, *fext;
+    // per-step particle data
+    double *qh, *jv_old, *F, *Vt, *du, *mf, *omega, *jv_new;
+    PartKernel pk;
+    // binning of particles into stage blocks
+    int32_t *blk_count, *blk_off, *blk_cursor, *blk_list;
+    // accumulators
+    double *sum_f, *sum_l;
+    // forcing profiles [IC_MAX_MODES][pmax]
+    double *prof;
+    // reductions and flags
+    double *red;
+    int32_t *flag;
+};
+
+struct Forcing {
+    int nmodes;
+    ic_mode modes[IC_MAX_MODES];
+};
+
+}  // namespace ic
+
+struct ic_ctx {
+    ic_params p;
+    hipStream_t stream;
+    int device;
+    bool bound;
+    void *f[4];
+    ic::Workspace ws;
+    int32_t np;
+    int64_t step;
+    int64_t nsamples;
+    ic::Forcing forcing;
+    int nblk[3];
+    int prof_stride;
+    std::string err;
+    // stage-kernel timing (ic_profile)
+    bool profiling;
+    std::vector<hipEvent_t> ev_pool;   // free events
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+    double prof_ms;
+    int64_t prof_launches;
+};
+
+namespace ic {
+
+size_t workspace_bytes(const ic_params &p, size_t *offsets_out = nullptr);
+void carve_workspace(const ic_params &p, char *base, Workspace &ws);
+int nblocks_total(const ic_params &p);
+
+// Launchers (ic_device.hip).  Each returns hipSuccess or the launch error.
+hipError_t launch_step(ic_ctx *c);
+hipError_t launch_interpolate(ic_ctx *c, int n, const double *q, int kind, const void *field,
+                              double *out);
+hipError_t launch_spread(ic_ctx *c, int n, const double *q, const double *f, int kind,
+                         void *field);
+hipError_t launch_init_velocity(ic_ctx *c);
+hipError_t launch_conserved(ic_ctx *c, double *host_out);
+
+// Event pair around one stage launch when profiling (nullptr otherwise).
+hipEvent_t prof_event(ic_ctx *c);
+void prof_push(ic_ctx *c, hipEvent_t a, hipEvent_t b);
+
+}  // namespace ic

@@ -1,0 +1,207 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Same seeded inputs on both sides; errors are e = max|x_gpu - x_oracle| /
+max|x_oracle| per field (drho, gx, gy, gz, u; q as a periodic distance in
+units of h).  Bar: FP64 e <= 1e-12 after several steps; FP32 e <= 1e-5 for
+one step from the same FP32-representable state.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ic_oracle as O
+from paper_1307_0702_amd import workloads as W
+from tests.oracle_state import make_state, modes_of
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _sim(w, prec="fp64", u=True):
+    from paper_1307_0702_amd.ic import Simulation
+    fl, p = w.fluid, w.particles
+    sim = Simulation(fl, prec=prec, max_particles=max(p.n, 1))
+    sim.set_state(w.drho, w.g)
+    if p.n:
+        from paper_1307_0702_amd import ic
+        eps = np.array([ic.ic_eps_from_kappa_ratio(fl.cf, r) for r in p.kappa_ratio])
+        sim.set_particles(p.q, p.me, eps, u=p.u if u else None, ks=p.ks, qeq=p.qeq, fext=p.fext)
+    if w.modes:
+        sim.set_forcing(modes_of(w))
+    return sim
+
+
+def _rel(a, b):
+    den = np.max(np.abs(b))
+    return np.max(np.abs(a - b)) / (den if den > 0 else 1.0)
+
+
+def _compare(sim, st, w, tol, label=""):
+    drho, g = sim.get_state()
+    errs = {"drho": _rel(drho, st["drho"])}
+    for a in range(3):
+        errs["g%d" % a] = _rel(g[a], st["g"][a])
+    if w.particles.n:
+        q, u = sim.get_particles()
+        errs["u"] = _rel(u, st["u"])
+        L = np.array([w.fluid.nx, w.fluid.ny, w.fluid.nz]) * w.fluid.h
+        dq = np.abs(q - st["q"])
+        dq = np.minimum(dq, L - dq)
+        errs["q"] = np.max(dq) / w.fluid.h
+    print(label, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= tol, (label, k, v)
+    return errs
+
+
+def _run_both(w, nsteps, prec="fp64", tol=1e-12, check_every=None):
+    print(f"case {w.name} grid {w.fluid.shape} np {w.particles.n} kT {w.fluid.kT} prec {prec}",
+          flush=True)
+    sim = _sim(w, prec)
+    st = make_state(w)
+    prm = w.fluid.as_dict()
+    modes = modes_of(w)
+    for n in range(nsteps):
+        sim.step(1)
+        st, _ = O.ic_step(st, prm, modes)
+        if check_every and (n + 1) % check_every == 0:
+            _compare(sim, st, w, tol, f"step {n + 1}")
+    _compare(sim, st, w, tol, f"step {nsteps}")
+    return sim, st
+
+
+def test_fp64_thermal_particles_ragged_multitile():
+    # 3 x 3 x 2 stage tiles, ragged in every direction; overlapping kernels
+    # allowed (Jacobi superposition of the no-slip corrections).
+    w = W.small_random(nx=70, ny=20, nz=40, npart=12, seed=21, kT=1e-3)
+    _run_both(w, 4, check_every=1)
+
+
+def test_fp64_deterministic_no_particles():
+    w = W.small_random(nx=33, ny=17, nz=35, npart=0, seed=5, kT=0.0)
+    w.modes = []
+    _run_both(w, 3)
+
+
+def test_fp64_plane_drive_nonoverlapping_particles_10_steps():
+    w = W.small_random(nx=24, ny=24, nz=24, npart=6, seed=8, kT=1e-3, min_sep=3.5)
+    w.modes = [W.Mode(axis=2, shape="plane", m=1, x0=7.2, amp=4e-3, omega=0.3),
+               W.Mode(axis=1, shape="cos", m=2, x0=0.0, amp=1e-3, omega=0.5, phase=1.0)]
+    _run_both(w, 10, check_every=5)
+
+
+def test_fp64_grid_smaller_than_tile():
+    w = W.small_random(nx=6, ny=5, nz=4, npart=2, seed=9, kT=1e-3)
+    _run_both(w, 3)
+
+
+def test_fp64_particles_on_periodic_seams():
+    w = W.small_random(nx=36, ny=12, nz=34, npart=6, seed=13, kT=1e-3)
+    L = np.array([36.0, 12.0, 34.0])
+    w.particles.q[:] = np.array([[0.0, 0.0, 0.0], [35.999999, 11.5, 33.9], [31.5, 8.0, 32.0],
+                                 [32.0, 7.5, 31.5], [0.5, 6.0, 16.0], [18.0, 0.25, 33.75]])
+    w.particles.qeq[:] = w.particles.q
+    _run_both(w, 3)
+
+
+def test_fp64_initial_velocity_from_no_slip():
+    w = W.small_random(nx=20, ny=16, nz=12, npart=4, seed=3, kT=0.0, min_sep=3.5)
+    w.particles.u = None
+    _run_both(w, 2)
+
+
+def test_fp32_one_step_from_fp32_state():
+    w = W.small_random(nx=70, ny=20, nz=40, npart=12, seed=31, kT=1e-3)
+    w.drho = w.drho.astype(np.float32).astype(np.float64)
+    w.g = w.g.astype(np.float32).astype(np.float64)
+    _run_both(w, 1, prec="fp32", tol=1e-5)
+
+
+def test_fp32_deterministic_one_step():
+    w = W.small_random(nx=40, ny=24, nz=33, npart=5, seed=41, kT=0.0)
+    w.drho = w.drho.astype(np.float32).astype(np.float64)
+    w.g = w.g.astype(np.float32).astype(np.float64)
+    _run_both(w, 1, prec="fp32", tol=1e-5)
+
+
+def test_avg_force_and_lambda_sums():
+    w = W.small_random(nx=24, ny=20, nz=22, npart=5, seed=17, kT=1e-3)
+    sim = _sim(w)
+    st = make_state(w)
+    prm = w.fluid.as_dict()
+    st, sF, sL = O.run(st, prm, 5, modes_of(w))
+    sim.step(5)
+    f, lam, ns = sim.avg_force(reset=True)
+    assert ns == 5
+    assert _rel(f, sF / 5) < 1e-12
+    assert _rel(lam, sL / 5) < 1e-10
+    f2, _, ns2 = sim.avg_force()
+    assert ns2 == 0 and np.all(f2 == 0)
+
+
+def test_conserved_sums_match_oracle():
+    w = W.small_random(nx=30, ny=14, nz=18, npart=4, seed=19, kT=1e-3)
+    sim = _sim(w)
+    st = make_state(w)
+    c_gpu = sim.conserved()
+    c_or = O.conserved(st, w.fluid.as_dict())
+    assert np.allclose(c_gpu, c_or, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+def test_interpolate_and_spread_match_oracle(kind):
+    from paper_1307_0702_amd.ic import Simulation
+    import torch
+    fl = W.Fluid(37, 19, 34, h=0.8)
+    rng = np.random.default_rng(kind)
+    sim = Simulation(fl, prec="fp64", max_particles=64)
+    L = np.array([fl.nx, fl.ny, fl.nz]) * fl.h
+    q = rng.random((50, 3)) * L
+    q[0] = [0.0, 0.0, 0.0]
+    q[1] = L - 1e-9
+    field = rng.standard_normal(fl.shape)
+    face = None if kind == 0 else kind - 1
+    got = sim.interpolate(q, kind, field)
+    want = O.interpolate(field, q, fl.h, face)
+    assert _rel(got, want) < 1e-13
+    f = rng.standard_normal(50)
+    out = torch.zeros(fl.shape, dtype=torch.float64, device="cuda:0")
+    sim.spread(q, f, kind, out)
+    want_s = O.spread(f, q, fl.h, fl.shape, face)
+    assert _rel(out.cpu().numpy(), want_s) < 1e-13
+
+
+def test_bitwise_repeatable():
+    w = W.small_random(nx=40, ny=16, nz=36, npart=10, seed=23, kT=1e-3)
+    a = _sim(w)
+    a.step(3)
+    b = _sim(w)
+    b.step(3)
+    ra, ga = a.get_state()
+    rb, gb = b.get_state()
+    assert np.array_equal(ra, rb)
+    for c in range(3):
+        assert np.array_equal(ga[c], gb[c])
+    assert np.array_equal(a.get_particles()[0], b.get_particles()[0])
+
+
+def test_error_codes_from_device_paths():
+    from paper_1307_0702_amd import ic
+    w = W.small_random(nx=16, ny=16, nz=16, npart=2, seed=2, kT=0.0)
+    sim = _sim(w)
+    with pytest.raises(ic.ICError) as e:
+        sim.set_particles(w.particles.q, np.array([-9.0, 0.0]), np.zeros(2))
+    assert e.value.code == ic.IC_E_MASS
+    with pytest.raises(ic.ICError) as e:
+        sim.set_particles(w.particles.q, np.zeros(2), np.array([0.0, 100.0]))
+    assert e.value.code == ic.IC_E_UNSTABLE
+    with pytest.raises(ic.ICError) as e:
+        sim.set_particles(np.zeros((5, 3)), np.zeros(5), np.zeros(5))
+    assert e.value.code == ic.IC_E_CAPACITY
