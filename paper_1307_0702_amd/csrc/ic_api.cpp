@@ -20,8 +20,16 @@ int tiles(int n, int t) { return (n + t - 1) / t; }
 
 }  // namespace
 
+// z extent of a stage block: the largest of 32, 16, 8 planes that still gives
+// at least 1024 blocks (four per compute unit), so small grids fill the chip.
+int choose_tz(const ic_params &p) {
+    int tz = 32;
+    while (tz > 8 && tiles(p.nx, TX) * tiles(p.ny, TY) * tiles(p.nz, tz) < 1024) tz /= 2;
+    return tz;
+}
+
 int nblocks_total(const ic_params &p) {
-    return tiles(p.nx, TX) * tiles(p.ny, TY) * tiles(p.nz, TZ);
+    return tiles(p.nx, TX) * tiles(p.ny, TY) * tiles(p.nz, choose_tz(p));
 }
 
 // Walks the workspace layout; with base == nullptr it only measures.
@@ -40,6 +48,7 @@ static size_t layout(const ic_params &p, char *base, Workspace *ws) {
     Workspace w{};
     for (int i = 0; i < 4; ++i) w.A[i] = take(ncell * esz);
     for (int i = 0; i < 4; ++i) w.B[i] = take(ncell * esz);
+    for (int i = 0; i < 9; ++i) w.N[i] = p.kT > 0.0 ? take(ncell * esz) : nullptr;
     auto d3 = [&]() { return (double *)take(3 * N * sizeof(double)); };
     auto d1 = [&]() { return (double *)take(N * sizeof(double)); };
     w.q = d3(); w.u = d3(); w.me = d1(); w.eps = d1(); w.ks = d1(); w.qeq = d3(); w.fext = d3();
@@ -53,6 +62,7 @@ static size_t layout(const ic_params &p, char *base, Workspace *ws) {
     w.blk_off = (int32_t *)take((nblk + 1) * sizeof(int32_t));
     w.blk_cursor = (int32_t *)take((nblk + 1) * sizeof(int32_t));
     w.blk_list = (int32_t *)take(N * MAX_BLOCKS_PER_PARTICLE * sizeof(int32_t));
+    w.blk_key = (int32_t *)take(N * MAX_BLOCKS_PER_PARTICLE * sizeof(int32_t));
     w.sum_f = d3(); w.sum_l = d3();
     w.prof = (double *)take((size_t)IC_MAX_MODES * pmax * sizeof(double));
     w.red = (double *)take(4 * 1024 * sizeof(double));
@@ -166,9 +176,10 @@ int ic_create(const ic_params *p, void *stream, ic_ctx **out) {
     c->step = 0;
     c->nsamples = 0;
     c->forcing.nmodes = 0;
+    c->tz = choose_tz(*p);
     c->nblk[0] = (p->nx + TX - 1) / TX;
     c->nblk[1] = (p->ny + TY - 1) / TY;
-    c->nblk[2] = (p->nz + TZ - 1) / TZ;
+    c->nblk[2] = (p->nz + c->tz - 1) / c->tz;
     int pmax = p->nx > p->ny ? p->nx : p->ny;
     if (p->nz > pmax) pmax = p->nz;
     c->prof_stride = pmax;
@@ -241,6 +252,10 @@ int ic_bind(ic_ctx *c, void *drho, void *gx, void *gy, void *gz, void *workspace
     c->nsamples = 0;
     c->forcing.nmodes = 0;
     hipError_t e = hipMemsetAsync(c->ws.flag, 0, 4 * sizeof(int32_t), c->stream);
+    // binning counters start at zero; the scan kernel re-zeroes them after use
+    if (e == hipSuccess)
+        e = hipMemsetAsync(c->ws.blk_count, 0, (nblocks_total(c->p) + 1) * sizeof(int32_t), c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "bind");
     c->bound = true;
     return IC_OK;

@@ -10,12 +10,14 @@
 // The fluid stage (the hot loop, three sweeps per step) is one kernel per RK
 // stage: each block owns a TX x TY column of cells and marches it along z,
 // keeping three planes of density, two of momentum and velocity and one of
-// fluxes in LDS, so every value is loaded from HBM once per sweep and every
-// flux and every random number is computed once (plus a one-cell ring of
-// halo fluxes).  Random numbers are drawn in-kernel from a counter-based
-// Philox generator keyed by (seed; cell, step, call, replica).  Particle
-// terms enter through per-block candidate lists built once per step (no
-// float atomics anywhere, so results are bitwise reproducible).
+// fluxes in LDS.  Every value is read from HBM once per sweep (plus a ring
+// one or two cells wide), the next plane is prefetched into registers while
+// the current one is computed, and every flux and random number is computed
+// once (plus a one-cell ring of halo fluxes).  Random numbers are drawn
+// in-kernel from a counter-based Philox generator keyed by (seed; cell, step,
+// call, replica).  Particle terms enter through per-block candidate lists
+// built once per step and sorted by plane.  There are no float atomics, so
+// results are bitwise reproducible.
 #include <math.h>
 
 #include "ic_internal.h"
@@ -36,15 +38,14 @@ __device__ __forceinline__ double phi3(double r) {
     return 0.0;
 }
 
-// The three kernel points along one axis reached from coordinate q: cell
-// centres sit at i h, faces at (i + 1/2) h.  Returns the first (wrapped)
-// index and the three weights.
-__device__ __forceinline__ int axis_points(double q, double inv_h, int n, bool face,
-                                           double w[3]) {
+// Weight of point d (0..2) among the three kernel points along one axis from
+// coordinate q (cell centres at i h, faces at (i + 1/2) h), and the first
+// (wrapped) point index.
+__device__ __forceinline__ int axis_point(double q, double inv_h, int n, bool face, int d,
+                                          double *w) {
     const double x = q * inv_h - (face ? 0.5 : 0.0);
     const double nearest = floor(x + 0.5);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) w[d] = phi3(x - (nearest - 1.0 + d));
+    *w = phi3(x - (nearest - 1.0 + d));
     int f = (int)nearest - 1;
     if (f < 0) f += n;
     if (f >= n) f -= n;
@@ -89,22 +90,12 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 }
 
 template <typename T>
-__device__ __forceinline__ T uniform23(uint32_t w);
-template <>
-__device__ __forceinline__ float uniform23<float>(uint32_t w) {
-    return ((float)(w >> 9) + 0.5f) * 0x1p-23f;
-}
-template <>
-__device__ __forceinline__ double uniform23<double>(uint32_t w) {
-    return ((double)(w >> 9) + 0.5) * 0x1p-23;
-}
-
-template <typename T>
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, T &z0, T &z1);
 template <>
 __device__ __forceinline__ void box_muller<double>(uint32_t a, uint32_t b, double &z0,
                                                    double &z1) {
-    const double u1 = uniform23<double>(a), u2 = uniform23<double>(b);
+    // uniforms ((x >> 9) + 1/2) 2^-23, exact in FP32 and FP64
+    const double u1 = ((double)(a >> 9) + 0.5) * 0x1p-23, u2 = ((double)(b >> 9) + 0.5) * 0x1p-23;
     const double r = sqrt(-2.0 * log(u1));
     double s, c;
     sincospi(2.0 * u2, &s, &c);
@@ -113,9 +104,10 @@ __device__ __forceinline__ void box_muller<double>(uint32_t a, uint32_t b, doubl
 }
 template <>
 __device__ __forceinline__ void box_muller<float>(uint32_t a, uint32_t b, float &z0, float &z1) {
-    const float u1 = uniform23<float>(a), u2 = uniform23<float>(b);
-    // v_log_f32 is log2; v_sin_f32 / v_cos_f32 take the angle in turns.
-    const float r = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
+    const float u1 = ((float)(a >> 9) + 0.5f) * 0x1p-23f, u2 = ((float)(b >> 9) + 0.5f) * 0x1p-23f;
+    // v_log_f32 is log2 (argument >= 2^-24, never denormal); v_sin/v_cos take
+    // the angle in turns.
+    const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
     z0 = r * __builtin_amdgcn_cosf(u2);
     z1 = r * __builtin_amdgcn_sinf(u2);
 }
@@ -124,50 +116,69 @@ struct NoiseKey {
     uint32_t k0, k1, step, replica;
 };
 
-// The six noise components of one cell for an RK stage, Z = W_A + wB W_B,
-// ordered xx, yy, zz, xy, xz, yz.  Philox calls: 0 -> A_xx A_yy A_zz A_xy,
-// 1 -> A_xz A_yz B_xz B_yz, 2 -> B_xx B_yy B_zz B_xy.
-template <typename T, bool WB>
-__device__ __forceinline__ void cell_noise(uint32_t cell, const NoiseKey &nk, T wB, T Z[6]) {
+enum { SEL_ALL = 0, SEL_DIAG = 1, SEL_EDGE = 2 };
+
+// The normals W_A and W_B of one cell and step, ordered xx, yy, zz, xy, xz,
+// yz.  Philox calls: 0 -> A_xx A_yy A_zz A_xy, 1 -> A_xz A_yz B_xz B_yz,
+// 2 -> B_xx B_yy B_zz B_xy (Box-Muller on word pairs (x,y) and (z,w)).
+// SEL_DIAG fills the xx, yy, zz entries only, SEL_EDGE xy, xz, yz only.
+template <typename T, int SEL>
+__device__ __forceinline__ void cell_normals(uint32_t cell, const NoiseKey &nk, T A[6], T B[6]) {
+    constexpr bool diag = SEL != SEL_EDGE, edge = SEL != SEL_DIAG;
     const U4 r0 = philox(cell, nk.step, 0u, nk.replica, nk.k0, nk.k1);
-    const U4 r1 = philox(cell, nk.step, 1u, nk.replica, nk.k0, nk.k1);
-    box_muller<T>(r0.x, r0.y, Z[0], Z[1]);
-    box_muller<T>(r0.z, r0.w, Z[2], Z[3]);
-    box_muller<T>(r1.x, r1.y, Z[4], Z[5]);
-    if (WB) {
-        T b[6];
-        box_muller<T>(r1.z, r1.w, b[4], b[5]);
-        const U4 r2 = philox(cell, nk.step, 2u, nk.replica, nk.k0, nk.k1);
-        box_muller<T>(r2.x, r2.y, b[0], b[1]);
-        box_muller<T>(r2.z, r2.w, b[2], b[3]);
-#pragma unroll
-        for (int c = 0; c < 6; ++c) Z[c] += wB * b[c];
+    if (diag) box_muller<T>(r0.x, r0.y, A[0], A[1]);
+    box_muller<T>(r0.z, r0.w, A[2], A[3]);
+    if (edge) {
+        const U4 r1 = philox(cell, nk.step, 1u, nk.replica, nk.k0, nk.k1);
+        box_muller<T>(r1.x, r1.y, A[4], A[5]);
+        box_muller<T>(r1.z, r1.w, B[4], B[5]);
     }
+    const U4 r2 = philox(cell, nk.step, 2u, nk.replica, nk.k0, nk.k1);
+    if (diag) box_muller<T>(r2.x, r2.y, B[0], B[1]);
+    box_muller<T>(r2.z, r2.w, B[2], B[3]);
+}
+
+// Discrete Landau-Lifshitz stress of one cell from its normals (Sec. IV B):
+// diagonal sd Z_aa + st (Z_xx + Z_yy + Z_zz) at the centre, off-diagonal
+// so Z_ab on the edges; sd = sqrt(2 eta kT) sqrt(2) / sqrt(h^3 dt),
+// st = (sqrt(zeta kT / 3) - sqrt(2 eta kT) / 3) sqrt(2) / sqrt(h^3 dt),
+// so = sqrt(2 eta kT) / sqrt(h^3 dt).
+template <typename T>
+__device__ __forceinline__ void ll_stress(const T Z[6], T sd, T st, T so, T S[6]) {
+    const T tr = st * (Z[0] + Z[1] + Z[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) S[c] = sd * Z[c] + tr;
+#pragma unroll
+    for (int c = 3; c < 6; ++c) S[c] = so * Z[c];
+}
+
+template <typename T>
+__device__ __forceinline__ T fast_rcp(T x);
+template <>
+__device__ __forceinline__ float fast_rcp<float>(float x) {
+    return __builtin_amdgcn_rcpf(x);
+}
+template <>
+__device__ __forceinline__ double fast_rcp<double>(double x) {
+    return 1.0 / x;
 }
 
 // ---------------------------------------------------------------------------
-// Fluid RK stage (App. A, SSP-RK3; fluxes of Sec. IV B with the staggered
-// discretisation described in ic_oracle's reading and the design notes).
+// Fluid RK stage (App. A, SSP-RK3; fluxes of Sec. IV B with the conservative
+// staggered discretisation given in the design notes).
 // ---------------------------------------------------------------------------
 template <typename T>
 struct StageArgs {
     const T *in[4];   // stage input U^s
     const T *un[4];   // U^n (stages 2 and 3)
     T *out[4];
-    int nx, ny, nz;
-    T rho0, cf2, eta, lam, inv_h, dt_h, dt, ra, rb, wB;
-    T sd, st, so;      // stochastic stress amplitudes (diag, trace, off-diagonal)
-    NoiseKey nk;
-    // particles at q^{n+1/2}
-    int np;
-    const int32_t *blk_off, *blk_list;
-    const int32_t *bc, *bf;
-    const double *wc, *wf, *omega, *F;
-    double inv_h3;
+    int nx, ny, nz, tz, gx, gy, gz;
+    T rho0, cf2, eta, lam, inv_h, dt_h, dt, ra, rb;
+    const T *noise[3]; // stochastic increment of this stage (x, y, z), NOISE only
     // imposed pressure: sum_m mamp[m] * prof[m][coord(maxis[m])]
     int nmodes;
     int maxis[IC_MAX_MODES];
-    double mamp[IC_MAX_MODES];
+    T mamp[IC_MAX_MODES];
     const double *prof;
     int pstride;
 };
@@ -178,172 +189,199 @@ constexpr int PS = PX * PY;
 
 __device__ __forceinline__ int lidx(int lx, int ly) { return (ly + 1) * PX + (lx + 1); }
 
-// Particle pressure sum_p Omega_p w_p / h^3 at cell (x, y, z) and the
-// imposed pressure there.
+// Imposed pressure at cell (x, y, z).  The particle pressure S Omega and the
+// spread force S F are added after the sweep (k_sparse, stage mode): both
+// enter the stage output linearly.
 template <typename T>
-__device__ __forceinline__ T extra_pressure(const StageArgs<T> &a, int cb, int ce, int x, int y,
-                                            int z) {
-    double p = 0.0;
-    for (int c = cb; c < ce; ++c) {
-        const int pid = a.blk_list[c];
-        int dz = z - a.bc[3 * pid + 2];
-        if (dz < 0) dz += a.nz;
-        if (dz >= 3) continue;
-        int dx = x - a.bc[3 * pid + 0];
-        if (dx < 0) dx += a.nx;
-        int dy = y - a.bc[3 * pid + 1];
-        if (dy < 0) dy += a.ny;
-        if (dx < 3 && dy < 3)
-            p += a.omega[pid] * a.wc[9 * pid + 0 + dx] * a.wc[9 * pid + 3 + dy] *
-                 a.wc[9 * pid + 6 + dz];
-    }
-    p *= a.inv_h3;
+__device__ __forceinline__ T ext_pressure(const StageArgs<T> &a, int x, int y, int z) {
+    T s = 0;
     for (int m = 0; m < a.nmodes; ++m) {
         const int ax = a.maxis[m];
         const int coord = ax == 0 ? x : (ax == 1 ? y : z);
-        p += a.mamp[m] * a.prof[m * a.pstride + coord];
+        s += a.mamp[m] * (T)a.prof[m * a.pstride + coord];
     }
-    return (T)p;
-}
-
-// Spread external force S_alpha F at the three faces of cell (x, y, z).
-template <typename T>
-__device__ __forceinline__ void face_force(const StageArgs<T> &a, int cb, int ce, int x, int y,
-                                           int z, T f[3]) {
-    double s[3] = {0.0, 0.0, 0.0};
-    for (int c = cb; c < ce; ++c) {
-        const int pid = a.blk_list[c];
-        const int32_t *bc = a.bc + 3 * pid, *bf = a.bf + 3 * pid;
-        const double *wc = a.wc + 9 * pid, *wf = a.wf + 9 * pid;
-        int cz = z - bc[2], fz = z - bf[2];
-        if (cz < 0) cz += a.nz;
-        if (fz < 0) fz += a.nz;
-        if (cz >= 3 && fz >= 3) continue;
-        int cx = x - bc[0], fx = x - bf[0], cy = y - bc[1], fy = y - bf[1];
-        if (cx < 0) cx += a.nx;
-        if (fx < 0) fx += a.nx;
-        if (cy < 0) cy += a.ny;
-        if (fy < 0) fy += a.ny;
-        const double *F = a.F + 3 * pid;
-        if (fx < 3 && cy < 3 && cz < 3) s[0] += F[0] * wf[0 + fx] * wc[3 + cy] * wc[6 + cz];
-        if (cx < 3 && fy < 3 && cz < 3) s[1] += F[1] * wc[0 + cx] * wf[3 + fy] * wc[6 + cz];
-        if (cx < 3 && cy < 3 && fz < 3) s[2] += F[2] * wc[0 + cx] * wc[3 + cy] * wf[6 + fz];
-    }
-    f[0] = (T)(s[0] * a.inv_h3);
-    f[1] = (T)(s[1] * a.inv_h3);
-    f[2] = (T)(s[2] * a.inv_h3);
+    return s;
 }
 
 template <typename T, int STAGE, bool NOISE>
 __global__ __launch_bounds__(STAGE_THREADS) void stage_kernel(const StageArgs<T> a) {
-    __shared__ T s_rho[3][PS];
-    __shared__ T s_g[2][3][PS];
+    // Rotating plane buffers.  With four density, three momentum, two
+    // (vx, vy) / three (vz) velocity planes, the update of plane k and the
+    // commit of plane k+2 touch disjoint buffers, so each plane needs only
+    // two barriers.
+    __shared__ T s_rho[4][PS];
+    __shared__ T s_g[3][3][PS];
     __shared__ T s_vx[2][PS], s_vy[2][PS], s_vz[3][PS];
     __shared__ T s_fl[6][PS];  // Pxx, Pyy, Pxy, Pyx, Pzx, Pzy at the current plane
 
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int nx = a.nx, ny = a.ny, nz = a.nz, tz = a.tz;
+    const int plane = nx * ny;
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
-    const int W = min(TX, nx - x0), Wy = min(TY, ny - y0), z1 = min(z0 + TZ, nz);
+    // Workgroups go to the 8 XCDs round-robin; give each XCD a contiguous run
+    // of tiles (x fastest) so tiles sharing halo lines share one L2.
+    int bx, by, bz;
+    {
+        const int nblk = a.gx * a.gy * a.gz, b = blockIdx.x;
+        const int per = nblk / 8, rem = nblk % 8, xcd = b % 8, idx = b / 8;
+        const int t = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+        bx = t % a.gx;
+        by = (t / a.gx) % a.gy;
+        bz = t / (a.gx * a.gy);
+    }
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * tz;
+    const int W = min(TX, nx - x0), Wy = min(TY, ny - y0), z1 = min(z0 + tz, nz);
     const int lx = tid % TX, ly = tid / TX;
     const bool own = lx < W && ly < Wy;
-    const int gxo = x0 + lx, gyo = y0 + ly;
+    const int xo = x0 + lx, yo = y0 + ly;
     const int li = lidx(lx, ly);
-    int cb = 0, ce = 0;
-    if (a.np > 0) {
-        const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        cb = a.blk_off[blk];
-        ce = a.blk_off[blk + 1];
-    }
+    const int own_xy = own ? yo * nx + xo : 0;
     const T rho0 = a.rho0, half = (T)0.5, quarter = (T)0.25;
-    const int nrr = (W + 3) * (Wy + 3);  // density region [-1, W+1] x [-1, Wy+1]
-    const int nrg = (W + 2) * (Wy + 2);  // momentum/velocity region [-1, W] x [-1, Wy]
 
-    auto gaddr = [&](int lxx, int lyy, int z) {
-        const int x = wrap(x0 + lxx, nx), y = wrap(y0 + lyy, ny);
-        return (size_t)((z * ny + y) * nx + x);
-    };
-    auto load_rho = [&](int p) {  // plane p (unwrapped) of density into LDS
-        const int z = wrap(p, nz);
-        T *dst = s_rho[(p + 3) % 3];
-        for (int i = tid; i < nrr; i += STAGE_THREADS) {
-            const int lxx = i % (W + 3) - 1, lyy = i / (W + 3) - 1;
-            dst[lidx(lxx, lyy)] = a.in[0][gaddr(lxx, lyy, z)];
+    // Load slots (fixed for the whole march): density region
+    // [-1, W+1] x [-1, Wy+1], momentum/velocity region [-1, W] x [-1, Wy].
+    const int wr = W + 3, nrr = wr * (Wy + 3);
+    const int wg = W + 2, nrg = wg * (Wy + 2);
+    int r_l[2], r_xy[2], g_l[2], g_xy[2];
+    bool r_ok[2], g_ok[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int i = tid + s * STAGE_THREADS;
+        r_ok[s] = i < nrr;
+        const int ir = r_ok[s] ? i : 0;
+        const int rx = ir % wr - 1, ry = ir / wr - 1;
+        r_l[s] = lidx(rx, ry);
+        r_xy[s] = wrap(y0 + ry, ny) * nx + wrap(x0 + rx, nx);
+        g_ok[s] = i < nrg;
+        const int ig = g_ok[s] ? i : 0;
+        const int gxx = ig % wg - 1, gyy = ig / wg - 1;
+        g_l[s] = lidx(gxx, gyy);
+        g_xy[s] = wrap(y0 + gyy, ny) * nx + wrap(x0 + gxx, nx);
+    }
+    // Halo flux items: wave 0 takes the +x column (xx) and +y row (yy), wave 1
+    // the -x column (yx, zx) and -y row (xy, zy), so each wave draws one kind
+    // of noise subset.
+    int h_type = -1, h_x = 0, h_y = 0;
+    {
+        const int i = tid < 64 ? tid : tid - 64;
+        if (tid < 128 && i < Wy + W) {
+            if (tid < 64) {
+                if (i < Wy) { h_type = 0; h_x = W; h_y = i; }
+                else { h_type = 1; h_x = i - Wy; h_y = Wy; }
+            } else {
+                if (i < Wy) { h_type = 2; h_x = -1; h_y = i; }
+                else { h_type = 3; h_x = i - Wy; h_y = -1; }
+            }
+        }
+    }
+    const int h_l = lidx(h_x, h_y);
+    const int h_gx = wrap(x0 + h_x, nx), h_gy = wrap(y0 + h_y, ny);
+    const int h_xy = h_gy * nx + h_gx;
+
+    // Register prefetch: density of plane p+1 on the density slots, momentum
+    // of plane p and density of plane p+1 on the momentum slots.
+    T pr[2] = {0, 0}, pg[2][3] = {{0, 0, 0}, {0, 0, 0}}, pz[2] = {0, 0};
+    auto prefetch = [&](int p) {
+        const int zg = wrap(p, nz) * plane, zr = wrap(p + 1, nz) * plane;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (r_ok[s]) pr[s] = a.in[0][zr + r_xy[s]];
+            if (g_ok[s]) {
+                pg[s][0] = a.in[1][zg + g_xy[s]];
+                pg[s][1] = a.in[2][zg + g_xy[s]];
+                pg[s][2] = a.in[3][zg + g_xy[s]];
+                pz[s] = a.in[0][zr + g_xy[s]];
+            }
         }
     };
-    // Momentum of plane p into LDS and velocity v = g / rho_face there; needs
-    // density of plane p in LDS and reads plane p+1 density for v^z.
-    auto load_g_vel = [&](int p) {
-        const int z = wrap(p, nz), zp = wrap(p + 1, nz);
-        const T *r = s_rho[(p + 3) % 3];
-        T *gx = s_g[(p + 2) & 1][0], *gy = s_g[(p + 2) & 1][1], *gz = s_g[(p + 2) & 1][2];
-        T *vx = s_vx[(p + 2) & 1], *vy = s_vy[(p + 2) & 1], *vz = s_vz[(p + 3) % 3];
-        for (int i = tid; i < nrg; i += STAGE_THREADS) {
-            const int lxx = i % (W + 2) - 1, lyy = i / (W + 2) - 1;
-            const size_t ga = gaddr(lxx, lyy, z);
-            const int l = lidx(lxx, lyy);
-            const T g0 = a.in[1][ga], g1 = a.in[2][ga], g2 = a.in[3][ga];
-            const T rz = a.in[0][gaddr(lxx, lyy, zp)];
-            gx[l] = g0;
-            gy[l] = g1;
-            gz[l] = g2;
-            vx[l] = g0 / (rho0 + half * (r[l] + r[l + 1]));
-            vy[l] = g1 / (rho0 + half * (r[l] + r[l + PX]));
-            vz[l] = g2 / (rho0 + half * (r[l] + rz));
+    // Plane buffers of the march, rotated once per plane.  Slot names are
+    // relative to the plane k being updated.
+    T *rb[4] = {s_rho[0], s_rho[1], s_rho[2], s_rho[3]};        // k-1 .. k+2
+    T *gb[3] = {s_g[0][0], s_g[1][0], s_g[2][0]};               // k, k+1, k+2
+    T *vxb[2] = {s_vx[0], s_vx[1]}, *vyb[2] = {s_vy[0], s_vy[1]};  // k, k+1
+    T *vzb[3] = {s_vz[0], s_vz[1], s_vz[2]};                     // k-1, k, k+1
+    // Writes density of plane p+1 into rw, momentum of plane p into gw and
+    // v = g / rho_face of plane p (density of plane p in r) into vxw/vyw/vzw.
+    auto commit = [&](T *rw, const T *r, T *gw, T *vxw, T *vyw, T *vzw) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (r_ok[s]) rw[r_l[s]] = pr[s];
+            if (g_ok[s]) {
+                const int l = g_l[s];
+                gw[l] = pg[s][0];
+                gw[PS + l] = pg[s][1];
+                gw[2 * PS + l] = pg[s][2];
+                vxw[l] = pg[s][0] * fast_rcp<T>(rho0 + half * (r[l] + r[l + 1]));
+                vyw[l] = pg[s][1] * fast_rcp<T>(rho0 + half * (r[l] + r[l + PX]));
+                vzw[l] = pg[s][2] * fast_rcp<T>(rho0 + half * (r[l] + pz[s]));
+            }
+        }
+    };
+    T un[4] = {0, 0, 0, 0}, nn[3] = {0, 0, 0};
+    auto prefetch_un = [&](int p) {
+        if (own && p < z1) {
+            const int g = p * plane + own_xy;
+            if (STAGE != 0) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) un[c] = a.un[c][g];
+            }
+            if (NOISE) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) nn[c] = a.noise[c][g];
+            }
         }
     };
 
-    // ---- prologue: planes z0-1 and z0 of density, plane z0-1 of momentum
-    load_rho(z0 - 1);
-    load_rho(z0);
+    // ---- prologue.  Iteration k = z0-1 only prepares carried values; in
+    // its slot naming density k-1 (= z0-2) is never used.
+    {
+        const int zr = wrap(z0 - 1, nz) * plane;
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+            if (r_ok[s]) rb[1][r_l[s]] = a.in[0][zr + r_xy[s]];     // density z0-1 (slot k)
+    }
+    prefetch(z0 - 1);
     __syncthreads();
-    load_g_vel(z0 - 1);
-    T Zc[6] = {0, 0, 0, 0, 0, 0}, Zn[6] = {0, 0, 0, 0, 0, 0};
-    if (NOISE && own)
-        cell_noise<T, STAGE != 2>((uint32_t)gaddr(lx, ly, wrap(z0 - 1, nz)), a.nk, a.wB, Zc);
+    commit(rb[2], rb[1], gb[0], vxb[0], vyb[0], vzb[1]);           // density z0, plane z0-1
+    prefetch(z0);
+    prefetch_un(z0);
     __syncthreads();
 
     T Pzz_cur = 0, Pxz_prev = 0, Pyz_prev = 0, gz_prev = 0, pex_cur = 0;
 
     for (int k = z0 - 1; k < z1; ++k) {
         const bool prep = (k == z0 - 1);
-        // ---- phase A: density of plane k+2, momentum and velocity of plane k+1
-        load_rho(k + 2);
-        load_g_vel(k + 1);
+        // ---- phase A: plane k+1 into LDS, then start loading plane k+2
+        commit(rb[3], rb[2], gb[1], vxb[1], vyb[1], vzb[2]);
+        const T un_cur[4] = {un[0], un[1], un[2], un[3]};
+        const T nn_cur[3] = {nn[0], nn[1], nn[2]};
+        if (k + 2 <= z1) prefetch(k + 2);
+        prefetch_un(k + 1);
         __syncthreads();
 
-        const T *rk = s_rho[(k + 3) % 3], *rk1 = s_rho[(k + 4) % 3];
-        const T *gx = s_g[(k + 2) & 1][0], *gy = s_g[(k + 2) & 1][1], *gz = s_g[(k + 2) & 1][2];
-        const T *gx1 = s_g[(k + 3) & 1][0], *gy1 = s_g[(k + 3) & 1][1],
-                *gz1 = s_g[(k + 3) & 1][2];
-        const T *vx = s_vx[(k + 2) & 1], *vy = s_vy[(k + 2) & 1], *vz = s_vz[(k + 3) % 3];
-        const T *vx1 = s_vx[(k + 3) & 1], *vy1 = s_vy[(k + 3) & 1], *vz1 = s_vz[(k + 4) % 3];
-        const T *vzm = s_vz[(k + 2) % 3];
+        const T *rk = rb[1], *rk1 = rb[2];
+        const T *gx = gb[0], *gy = gb[0] + PS, *gz = gb[0] + 2 * PS;
+        const T *gx1 = gb[1], *gy1 = gb[1] + PS, *gz1 = gb[1] + 2 * PS;
+        const T *vx = vxb[0], *vy = vyb[0], *vz = vzb[1];
+        const T *vx1 = vxb[1], *vy1 = vyb[1], *vz1 = vzb[2];
+        const T *vzm = vzb[0];
         const int zk = wrap(k, nz), zk1 = wrap(k + 1, nz);
 
         // ---- phase B: fluxes
         T Pzz_next = 0, Pxz_cur = 0, Pyz_cur = 0, pex_next = 0;
         if (own) {
-            if (NOISE)
-                cell_noise<T, STAGE != 2>((uint32_t)gaddr(lx, ly, zk1), a.nk, a.wB, Zn);
             // centre flux zz at plane k+1
-            pex_next = extra_pressure(a, cb, ce, gxo, gyo, zk1);
+            pex_next = ext_pressure(a, xo, yo, zk1);
             const int l = li;
             const T div1 = ((vx1[l] - vx1[l - 1]) + (vy1[l] - vy1[l - PX]) + (vz1[l] - vz[l])) *
                            a.inv_h;
             T pzz = a.cf2 * rk1[l] + pex_next + quarter * (gz1[l] + gz[l]) * (vz1[l] + vz[l]) -
                     (2 * a.eta * (vz1[l] - vz[l]) * a.inv_h + a.lam * div1);
-            if (NOISE) pzz -= a.sd * Zn[2] + a.st * (Zn[0] + Zn[1] + Zn[2]);
             Pzz_next = pzz;
             // edge fluxes along z at plane k (own column only)
             const T viz_x = a.eta * ((vx1[l] - vx[l]) + (vz[l + 1] - vz[l])) * a.inv_h;
             const T viz_y = a.eta * ((vy1[l] - vy[l]) + (vz[l + PX] - vz[l])) * a.inv_h;
             Pxz_cur = quarter * (gx[l] + gx1[l]) * (vz[l] + vz[l + 1]) - viz_x;
             Pyz_cur = quarter * (gy[l] + gy1[l]) * (vz[l] + vz[l + PX]) - viz_y;
-            if (NOISE) {
-                Pxz_cur -= a.so * Zc[4];
-                Pyz_cur -= a.so * Zc[5];
-            }
             if (!prep) {
                 const T pi = a.cf2 * rk[l] + pex_cur;
                 const T div = ((vx[l] - vx[l - 1]) + (vy[l] - vy[l - PX]) + (vz[l] - vzm[l])) *
@@ -357,15 +395,6 @@ __global__ __launch_bounds__(STAGE_THREADS) void stage_kernel(const StageArgs<T>
                 T pyx = quarter * (gy[l] + gy[l + 1]) * (vx[l] + vx[l + PX]) - vxy;
                 T pzx = quarter * (gz[l] + gz[l + 1]) * (vx[l] + vx1[l]) - viz_x;
                 T pzy = quarter * (gz[l] + gz[l + PX]) * (vy[l] + vy1[l]) - viz_y;
-                if (NOISE) {
-                    const T tr = a.st * (Zc[0] + Zc[1] + Zc[2]);
-                    pxx -= a.sd * Zc[0] + tr;
-                    pyy -= a.sd * Zc[1] + tr;
-                    pxy -= a.so * Zc[3];
-                    pyx -= a.so * Zc[3];
-                    pzx -= a.so * Zc[4];
-                    pzy -= a.so * Zc[5];
-                }
                 s_fl[0][l] = pxx;
                 s_fl[1][l] = pyy;
                 s_fl[2][l] = pxy;
@@ -374,90 +403,59 @@ __global__ __launch_bounds__(STAGE_THREADS) void stage_kernel(const StageArgs<T>
                 s_fl[5][l] = pzy;
             }
         }
-        if (!prep) {
-            // ring of halo fluxes at plane k: +x column (xx), +y row (yy),
-            // -x column (yx, zx), -y row (xy, zy)
-            const int nh = 2 * (W + Wy);
-            for (int i = tid; i < nh; i += STAGE_THREADS) {
-                int hx, hy, type;
-                if (i < Wy) {
-                    hx = W; hy = i; type = 0;
-                } else if (i < Wy + W) {
-                    hx = i - Wy; hy = Wy; type = 1;
-                } else if (i < 2 * Wy + W) {
-                    hx = -1; hy = i - Wy - W; type = 2;
-                } else {
-                    hx = i - 2 * Wy - W; hy = -1; type = 3;
-                }
-                const int l = lidx(hx, hy);
-                T Z[6] = {0, 0, 0, 0, 0, 0};
-                if (NOISE) cell_noise<T, STAGE != 2>((uint32_t)gaddr(hx, hy, zk), a.nk, a.wB, Z);
-                if (type <= 1) {
-                    const T pe = extra_pressure(a, cb, ce, wrap(x0 + hx, nx), wrap(y0 + hy, ny), zk);
-                    const T pi = a.cf2 * rk[l] + pe;
-                    const T div = ((vx[l] - vx[l - 1]) + (vy[l] - vy[l - PX]) + (vz[l] - vzm[l])) *
-                                  a.inv_h;
-                    const T tr = NOISE ? a.st * (Z[0] + Z[1] + Z[2]) : (T)0;
-                    if (type == 0) {
-                        T pxx = pi + quarter * (gx[l] + gx[l - 1]) * (vx[l] + vx[l - 1]) -
-                                (2 * a.eta * (vx[l] - vx[l - 1]) * a.inv_h + a.lam * div);
-                        if (NOISE) pxx -= a.sd * Z[0] + tr;
-                        s_fl[0][l] = pxx;
-                    } else {
-                        T pyy = pi + quarter * (gy[l] + gy[l - PX]) * (vy[l] + vy[l - PX]) -
-                                (2 * a.eta * (vy[l] - vy[l - PX]) * a.inv_h + a.lam * div);
-                        if (NOISE) pyy -= a.sd * Z[1] + tr;
-                        s_fl[1][l] = pyy;
-                    }
-                } else if (type == 2) {
-                    const T vxy = a.eta * ((vx[l + PX] - vx[l]) + (vy[l + 1] - vy[l])) * a.inv_h;
+        if (!prep && h_type >= 0) {
+            const int l = h_l;
+            if (h_type <= 1) {
+                const T pi = a.cf2 * rk[l] + ext_pressure(a, h_gx, h_gy, zk);
+                const T div = ((vx[l] - vx[l - 1]) + (vy[l] - vy[l - PX]) + (vz[l] - vzm[l])) *
+                              a.inv_h;
+                if (h_type == 0)
+                    s_fl[0][l] = pi + quarter * (gx[l] + gx[l - 1]) * (vx[l] + vx[l - 1]) -
+                                 (2 * a.eta * (vx[l] - vx[l - 1]) * a.inv_h + a.lam * div);
+                else
+                    s_fl[1][l] = pi + quarter * (gy[l] + gy[l - PX]) * (vy[l] + vy[l - PX]) -
+                                 (2 * a.eta * (vy[l] - vy[l - PX]) * a.inv_h + a.lam * div);
+            } else {
+                const T vxy = a.eta * ((vx[l + PX] - vx[l]) + (vy[l + 1] - vy[l])) * a.inv_h;
+                if (h_type == 2) {
                     const T viz_x = a.eta * ((vx1[l] - vx[l]) + (vz[l + 1] - vz[l])) * a.inv_h;
-                    T pyx = quarter * (gy[l] + gy[l + 1]) * (vx[l] + vx[l + PX]) - vxy;
-                    T pzx = quarter * (gz[l] + gz[l + 1]) * (vx[l] + vx1[l]) - viz_x;
-                    if (NOISE) {
-                        pyx -= a.so * Z[3];
-                        pzx -= a.so * Z[4];
-                    }
-                    s_fl[3][l] = pyx;
-                    s_fl[4][l] = pzx;
+                    s_fl[3][l] = quarter * (gy[l] + gy[l + 1]) * (vx[l] + vx[l + PX]) - vxy;
+                    s_fl[4][l] = quarter * (gz[l] + gz[l + 1]) * (vx[l] + vx1[l]) - viz_x;
                 } else {
-                    const T vxy = a.eta * ((vx[l + PX] - vx[l]) + (vy[l + 1] - vy[l])) * a.inv_h;
                     const T viz_y = a.eta * ((vy1[l] - vy[l]) + (vz[l + PX] - vz[l])) * a.inv_h;
-                    T pxy = quarter * (gx[l] + gx[l + PX]) * (vy[l] + vy[l + 1]) - vxy;
-                    T pzy = quarter * (gz[l] + gz[l + PX]) * (vy[l] + vy1[l]) - viz_y;
-                    if (NOISE) {
-                        pxy -= a.so * Z[3];
-                        pzy -= a.so * Z[5];
-                    }
-                    s_fl[2][l] = pxy;
-                    s_fl[5][l] = pzy;
+                    s_fl[2][l] = quarter * (gx[l] + gx[l + PX]) * (vy[l] + vy[l + 1]) - vxy;
+                    s_fl[5][l] = quarter * (gz[l] + gz[l + PX]) * (vy[l] + vy1[l]) - viz_y;
                 }
             }
         }
         __syncthreads();
 
-        // ---- phase C: update of plane k
+        // ---- phase C: update of plane k (no barrier after it: the next
+        // commit writes buffers this phase does not read)
         if (!prep && own) {
             const int l = li;
-            T f[3] = {0, 0, 0};
-            if (ce > cb) face_force(a, cb, ce, gxo, gyo, zk, f);
             const T drho = -a.dt_h * ((gx[l] - gx[l - 1]) + (gy[l] - gy[l - PX]) + (gz[l] - gz_prev));
             const T dgx = -a.dt_h * ((s_fl[0][l + 1] - s_fl[0][l]) + (s_fl[2][l] - s_fl[2][l - PX]) +
-                                     (Pxz_cur - Pxz_prev)) + a.dt * f[0];
+                                     (Pxz_cur - Pxz_prev));
             const T dgy = -a.dt_h * ((s_fl[1][l + PX] - s_fl[1][l]) + (s_fl[3][l] - s_fl[3][l - 1]) +
-                                     (Pyz_cur - Pyz_prev)) + a.dt * f[1];
+                                     (Pyz_cur - Pyz_prev));
             const T dgz = -a.dt_h * ((Pzz_next - Pzz_cur) + (s_fl[4][l] - s_fl[4][l - 1]) +
-                                     (s_fl[5][l] - s_fl[5][l - PX])) + a.dt * f[2];
-            const size_t g = gaddr(lx, ly, zk);
+                                     (s_fl[5][l] - s_fl[5][l - PX]));
+            const int g = zk * plane + own_xy;
             const T us[4] = {rk[l], gx[l], gy[l], gz[l]};
-            const T d[4] = {drho, dgx, dgy, dgz};
+            T d[4] = {drho, dgx, dgy, dgz};
+            if (NOISE) {
+                d[1] += nn_cur[0];
+                d[2] += nn_cur[1];
+                d[3] += nn_cur[2];
+            }
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 T v;
                 if (STAGE == 0)
                     v = us[c] + d[c];
                 else
-                    v = a.ra * a.un[c][g] + a.rb * (us[c] + d[c]);
+                    v = a.ra * un_cur[c] + a.rb * (us[c] + d[c]);
                 a.out[c][g] = v;
             }
         }
@@ -466,15 +464,157 @@ __global__ __launch_bounds__(STAGE_THREADS) void stage_kernel(const StageArgs<T>
         Pxz_prev = Pxz_cur;
         Pyz_prev = Pyz_cur;
         pex_cur = pex_next;
+        // rotate: density k-1 <- k <- k+1 <- k+2, momentum k <- k+1 <- k+2,
+        // velocities k-1 <- k <- k+1
+        {
+            T *t = rb[0];
+            rb[0] = rb[1]; rb[1] = rb[2]; rb[2] = rb[3]; rb[3] = t;
+            t = gb[0];
+            gb[0] = gb[1]; gb[1] = gb[2]; gb[2] = t;
+            t = vxb[0]; vxb[0] = vxb[1]; vxb[1] = t;
+            t = vyb[0]; vyb[0] = vyb[1]; vyb[1] = t;
+            t = vzb[0];
+            vzb[0] = vzb[1]; vzb[1] = vzb[2]; vzb[2] = t;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stochastic increments of one step.  The stochastic flux enters each RK
+// stage linearly and does not depend on the state, so its increment
+// N(W) = -(dt/h) div(-Sigma(W)) is computed once per step for W_A and W_B
+// and written as N1 = N(W_A) - sqrt(3) N(W_B), N2 = N(W_A) + sqrt(3) N(W_B),
+// N3 = N(W_A) for the three stages (App. A, weak third-order combinations).
+// Same column march as the stage kernel; ring cells draw only the normals
+// their neighbours need.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct NoiseArgs {
+    T *out[9];
+    int nx, ny, nz, tz, gx, gy, gz;
+    T dt_h, sd, st, so, s3;
+    NoiseKey nk;
+};
+
+template <typename T>
+__global__ __launch_bounds__(STAGE_THREADS) void noise_kernel(const NoiseArgs<T> a) {
+    __shared__ T s_S[2][5][PS];  // [W_A, W_B][xx, yy, xy, xz, yz] at the current plane
+    const int nx = a.nx, ny = a.ny, nz = a.nz, tz = a.tz;
+    const int plane = nx * ny;
+    const int tid = threadIdx.x;
+    int bx, by, bz;
+    {
+        const int nblk = a.gx * a.gy * a.gz, b = blockIdx.x;
+        const int per = nblk / 8, rem = nblk % 8, xcd = b % 8, idx = b / 8;
+        const int t = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+        bx = t % a.gx;
+        by = (t / a.gx) % a.gy;
+        bz = t / (a.gx * a.gy);
+    }
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * tz;
+    const int W = min(TX, nx - x0), Wy = min(TY, ny - y0), z1 = min(z0 + tz, nz);
+    const int lx = tid % TX, ly = tid / TX;
+    const bool own = lx < W && ly < Wy;
+    const int li = lidx(lx, ly);
+    const int own_xy = own ? (y0 + ly) * nx + x0 + lx : 0;
+    int h_type = -1, h_x = 0, h_y = 0;
+    {
+        const int i = tid < 64 ? tid : tid - 64;
+        if (tid < 128 && i < Wy + W) {
+            if (tid < 64) {
+                if (i < Wy) { h_type = 0; h_x = W; h_y = i; }
+                else { h_type = 1; h_x = i - Wy; h_y = Wy; }
+            } else {
+                if (i < Wy) { h_type = 2; h_x = -1; h_y = i; }
+                else { h_type = 3; h_x = i - Wy; h_y = -1; }
+            }
+        }
+    }
+    const int h_l = lidx(h_x, h_y);
+    const int h_xy = wrap(y0 + h_y, ny) * nx + wrap(x0 + h_x, nx);
+
+    // own stresses: planes k and k+1 (all components), plane k-1 (xz, yz)
+    T SAc[6] = {0, 0, 0, 0, 0, 0}, SBc[6] = {0, 0, 0, 0, 0, 0};
+    T SAp[6] = {0, 0, 0, 0, 0, 0}, SBp[6] = {0, 0, 0, 0, 0, 0};
+    if (own) {
+        T A[6] = {0, 0, 0, 0, 0, 0}, B[6] = {0, 0, 0, 0, 0, 0};
+        cell_normals<T, SEL_EDGE>((uint32_t)(wrap(z0 - 1, nz) * plane + own_xy), a.nk, A, B);
+        ll_stress(A, a.sd, a.st, a.so, SAp);
+        ll_stress(B, a.sd, a.st, a.so, SBp);
+        cell_normals<T, SEL_ALL>((uint32_t)(z0 * plane + own_xy), a.nk, A, B);
+        ll_stress(A, a.sd, a.st, a.so, SAc);
+        ll_stress(B, a.sd, a.st, a.so, SBc);
+    }
+    for (int k = z0; k < z1; ++k) {
+        T SAn[6] = {0, 0, 0, 0, 0, 0}, SBn[6] = {0, 0, 0, 0, 0, 0};
+        if (own) {
+            T A[6], B[6];
+            cell_normals<T, SEL_ALL>((uint32_t)(wrap(k + 1, nz) * plane + own_xy), a.nk, A, B);
+            ll_stress(A, a.sd, a.st, a.so, SAn);
+            ll_stress(B, a.sd, a.st, a.so, SBn);
+            const int l = li;
+            s_S[0][0][l] = SAc[0]; s_S[0][1][l] = SAc[1]; s_S[0][2][l] = SAc[3];
+            s_S[0][3][l] = SAc[4]; s_S[0][4][l] = SAc[5];
+            s_S[1][0][l] = SBc[0]; s_S[1][1][l] = SBc[1]; s_S[1][2][l] = SBc[3];
+            s_S[1][3][l] = SBc[4]; s_S[1][4][l] = SBc[5];
+        }
+        if (h_type >= 0) {
+            T A[6] = {0, 0, 0, 0, 0, 0}, B[6] = {0, 0, 0, 0, 0, 0}, SA[6], SB[6];
+            const uint32_t hc = (uint32_t)(k * plane + h_xy);
+            if (h_type <= 1)
+                cell_normals<T, SEL_DIAG>(hc, a.nk, A, B);
+            else
+                cell_normals<T, SEL_EDGE>(hc, a.nk, A, B);
+            ll_stress(A, a.sd, a.st, a.so, SA);
+            ll_stress(B, a.sd, a.st, a.so, SB);
+            const int l = h_l;
+            if (h_type == 0) {
+                s_S[0][0][l] = SA[0]; s_S[1][0][l] = SB[0];
+            } else if (h_type == 1) {
+                s_S[0][1][l] = SA[1]; s_S[1][1][l] = SB[1];
+            } else if (h_type == 2) {
+                s_S[0][2][l] = SA[3]; s_S[1][2][l] = SB[3];
+                s_S[0][3][l] = SA[4]; s_S[1][3][l] = SB[4];
+            } else {
+                s_S[0][2][l] = SA[3]; s_S[1][2][l] = SB[3];
+                s_S[0][4][l] = SA[5]; s_S[1][4][l] = SB[5];
+            }
+        }
+        __syncthreads();
+        if (own) {
+            const int l = li;
+            T N[2][3];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) Zc[c] = Zn[c];
+            for (int w = 0; w < 2; ++w) {
+                const T *Sc = w == 0 ? SAc : SBc, *Sp = w == 0 ? SAp : SBp, *Sn = w == 0 ? SAn : SBn;
+                const T *xx = s_S[w][0], *yy = s_S[w][1], *xy = s_S[w][2], *xz = s_S[w][3],
+                        *yz = s_S[w][4];
+                N[w][0] = a.dt_h * ((xx[l + 1] - xx[l]) + (xy[l] - xy[l - PX]) + (Sc[4] - Sp[4]));
+                N[w][1] = a.dt_h * ((yy[l + PX] - yy[l]) + (xy[l] - xy[l - 1]) + (Sc[5] - Sp[5]));
+                N[w][2] = a.dt_h * ((Sn[2] - Sc[2]) + (xz[l] - xz[l - 1]) + (yz[l] - yz[l - PX]));
+            }
+            const int g = k * plane + own_xy;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                a.out[c][g] = N[0][c] - a.s3 * N[1][c];
+                a.out[3 + c][g] = N[0][c] + a.s3 * N[1][c];
+                a.out[6 + c][g] = N[0][c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            SAp[c] = SAc[c]; SBp[c] = SBc[c];
+            SAc[c] = SAn[c]; SBc[c] = SBn[c];
+        }
         __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// Particle kernels: one 64-lane wave per particle; the 27-point sums are
-// reduced with a fixed butterfly so results do not depend on timing.
+// Particle kernels: one 64-lane wave per particle.  Lanes 0..17 hold the 18
+// kernel weights (3 axes x {cell, face} x 3 points) and lanes 18..23 the
+// first point indices; 27-point sums are reduced with a fixed butterfly, so
+// results do not depend on timing.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -487,26 +627,47 @@ struct Grid {
     double h, inv_h, rho0;
 };
 
-// Kernel point `pt` (0..26, x fastest) of location `kind` (0 cell, 1+a face
-// a) around q: global element index and weight prod phi.
-__device__ __forceinline__ void stencil_point(const Grid &G, const double q[3], int kind, int pt,
-                                              size_t *idx, double *w) {
-    const int d[3] = {pt % 3, (pt / 3) % 3, pt / 9};
-    int c[3];
-    double wt = 1.0;
+struct WaveKernel {
+    double w;   // lanes 0..17
+    int first;  // lanes 18..23
+};
+
+__device__ __forceinline__ WaveKernel wave_kernel(const Grid &G, const double q[3]) {
+    const int lane = threadIdx.x & 63;
     const int n[3] = {G.nx, G.ny, G.nz};
+    WaveKernel k{0.0, 0};
+    if (lane < 24) {
+        const int ax = lane < 18 ? lane / 6 : (lane - 18) % 3;
+        const bool face = lane < 18 ? (lane % 6) >= 3 : lane >= 21;
+        const int d = lane < 18 ? lane % 3 : 0;
+        double w;
+        const int f = axis_point(q[ax], G.inv_h, n[ax], face, d, &w);
+        if (lane < 18)
+            k.w = w;
+        else
+            k.first = f;
+    }
+    return k;
+}
+
+// Weight and element index of kernel point pt (0..26, x fastest) of location
+// kind (0 cell, 1+a face a).  Every lane of the wave must call it.
+__device__ __forceinline__ void wave_point(const Grid &G, const WaveKernel &k, int kind, int pt,
+                                           size_t *idx, double *w) {
+    const int d[3] = {pt % 3, (pt / 3) % 3, pt / 9};
+    const int n[3] = {G.nx, G.ny, G.nz};
+    double wt = 1.0;
+    int c[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-        double ww[3];
-        const int f = axis_points(q[ax], G.inv_h, n[ax], kind == ax + 1, ww);
-        c[ax] = wrap(f + d[ax], n[ax]);
-        wt *= ww[d[ax]];
+        const bool face = kind == ax + 1;
+        wt *= __shfl(k.w, ax * 6 + (face ? 3 : 0) + d[ax], 64);
+        c[ax] = wrap(__shfl(k.first, 18 + (face ? 3 : 0) + ax, 64) + d[ax], n[ax]);
     }
     *idx = ((size_t)c[2] * G.ny + c[1]) * G.nx + c[0];
     *w = wt;
 }
 
-// Face neighbour (+1 along axis ax) of element index i.
 __device__ __forceinline__ size_t plus_one(const Grid &G, size_t i, int ax) {
     const int x = (int)(i % G.nx), y = (int)((i / G.nx) % G.ny), z = (int)(i / ((size_t)G.nx * G.ny));
     int c[3] = {x, y, z};
@@ -515,31 +676,41 @@ __device__ __forceinline__ size_t plus_one(const Grid &G, size_t i, int ax) {
     return ((size_t)c[2] * G.ny + c[1]) * G.nx + c[0];
 }
 
-// J_alpha (g^alpha / rho_face^alpha) for alpha = 0, 1, 2 at q; every lane of
-// the wave gets the result.
+// Sums over the 81 (component, point) pairs of the face kernels at q:
+// sv[a] = J_a (g^a / rho_face^a) and, if sm, sm[a] = J_a rho_face^a.
 template <typename T>
-__device__ __forceinline__ void wave_velocity(const Grid &G, const T *const f[4], const double q[3],
-                                              double out[3]) {
+__device__ __forceinline__ void wave_face_sums(const Grid &G, const T *const f[4], const double q[3],
+                                               double sv[3], double *sm) {
     const int lane = threadIdx.x & 63;
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (int item = lane; item < 81; item += 64) {
-        const int ax = item / 27, pt = item % 27;
+    const WaveKernel k = wave_kernel(G, q);
+    double av[3] = {0, 0, 0}, am[3] = {0, 0, 0};
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const int item = lane + 64 * it;
+        const bool valid = item < 81;
+        const int itm = valid ? item : 0;
+        const int ax = itm / 27, pt = itm % 27;
         size_t i;
         double w;
-        stencil_point(G, q, ax + 1, pt, &i, &w);
-        const size_t j = plus_one(G, i, ax);
-        const double rf = G.rho0 + 0.5 * ((double)f[0][i] + (double)f[0][j]);
-        acc[ax] += w * ((double)f[1 + ax][i] / rf);
+        wave_point(G, k, ax + 1, pt, &i, &w);
+        if (valid) {
+            const size_t j = plus_one(G, i, ax);
+            const double rf = G.rho0 + 0.5 * ((double)f[0][i] + (double)f[0][j]);
+            av[ax] += w * ((double)f[1 + ax][i] / rf);
+            am[ax] += w * rf;
+        }
     }
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) out[ax] = wave_sum(acc[ax]);
+    for (int ax = 0; ax < 3; ++ax) {
+        sv[ax] = wave_sum(av[ax]);
+        if (sm) sm[ax] = wave_sum(am[ax]);
+    }
 }
 
 template <typename T>
 struct PartArgs {
     Grid G;
-    const T *f[4];   // fields read by the kernel
-    T *fw[4];        // fields written (correction)
+    const T *f[4];
     int np;
     double dt, V, L[3];
     double *q, *u, *me, *eps, *ks, *qeq, *fext;
@@ -550,46 +721,64 @@ struct PartArgs {
     int32_t *flag;
 };
 
-// Substeps 1-2 and the kernel weights at q^{n+1/2} (App. A).
+// Substeps 1-2 and the kernel data at q^{n+1/2} (App. A).
 template <typename T>
 __global__ __launch_bounds__(256) void k_pre(const PartArgs<T> a) {
     const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (p >= a.np) return;
     const int lane = threadIdx.x & 63;
-    double q[3] = {a.q[3 * p], a.q[3 * p + 1], a.q[3 * p + 2]};
+    const double q[3] = {a.q[3 * p], a.q[3 * p + 1], a.q[3 * p + 2]};
     double U[3];
-    wave_velocity<T>(a.G, a.f, q, U);                         // J^n v^n at q^n
+    wave_face_sums<T>(a.G, a.f, q, U, nullptr);           // J^n v^n at q^n
     double qh[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) qh[ax] = wrap_pos(q[ax] + 0.5 * a.dt * U[ax], a.L[ax]);
     double jv[3];
-    wave_velocity<T>(a.G, a.f, qh, jv);                       // J^{n+1/2} v^n
-    if (lane == 0) {
-        const int n[3] = {a.G.nx, a.G.ny, a.G.nz};
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            a.qh[3 * p + ax] = qh[ax];
-            a.jv_old[3 * p + ax] = jv[ax];
-            a.F[3 * p + ax] = -a.ks[p] * min_image(qh[ax] - a.qeq[3 * p + ax], a.L[ax]) +
-                              a.fext[3 * p + ax];
-            a.bc[3 * p + ax] = axis_points(qh[ax], a.G.inv_h, n[ax], false, a.wc + 9 * p + 3 * ax);
-            a.bf[3 * p + ax] = axis_points(qh[ax], a.G.inv_h, n[ax], true, a.wf + 9 * p + 3 * ax);
-        }
+    wave_face_sums<T>(a.G, a.f, qh, jv, nullptr);         // J^{n+1/2} v^n
+    const WaveKernel k = wave_kernel(a.G, qh);
+    if (lane < 18) {
+        const int ax = lane / 6, d = lane % 3;
+        if ((lane % 6) < 3)
+            a.wc[9 * p + 3 * ax + d] = k.w;
+        else
+            a.wf[9 * p + 3 * ax + d] = k.w;
+    } else if (lane < 24) {
+        if (lane < 21)
+            a.bc[3 * p + lane - 18] = k.first;
+        else
+            a.bf[3 * p + lane - 21] = k.first;
+    } else if (lane < 27) {
+        const int ax = lane - 24;
+        a.qh[3 * p + ax] = qh[ax];
+        a.jv_old[3 * p + ax] = jv[ax];
+        a.F[3 * p + ax] = -a.ks[p] * min_image(qh[ax] - a.qeq[3 * p + ax], a.L[ax]) +
+                          a.fext[3 * p + ax];
     }
 }
 
 // Kernel data for standalone spreading at caller positions.
-__global__ void k_weights(const Grid G, int np, const double *q, double *qh, int32_t *bc,
-                          int32_t *bf, double *wc, double *wf) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_weights(const Grid G, int np, const double *q, double *qh,
+                                                 int32_t *bc, int32_t *bf, double *wc, double *wf) {
+    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (p >= np) return;
-    const int n[3] = {G.nx, G.ny, G.nz};
+    const int lane = threadIdx.x & 63;
     const double L[3] = {G.nx * G.h, G.ny * G.h, G.nz * G.h};
-    for (int ax = 0; ax < 3; ++ax) {
-        const double x = wrap_pos(q[3 * p + ax], L[ax]);
-        qh[3 * p + ax] = x;
-        bc[3 * p + ax] = axis_points(x, G.inv_h, n[ax], false, wc + 9 * p + 3 * ax);
-        bf[3 * p + ax] = axis_points(x, G.inv_h, n[ax], true, wf + 9 * p + 3 * ax);
+    const double x[3] = {wrap_pos(q[3 * p], L[0]), wrap_pos(q[3 * p + 1], L[1]),
+                         wrap_pos(q[3 * p + 2], L[2])};
+    const WaveKernel k = wave_kernel(G, x);
+    if (lane < 18) {
+        const int ax = lane / 6, d = lane % 3;
+        if ((lane % 6) < 3)
+            wc[9 * p + 3 * ax + d] = k.w;
+        else
+            wf[9 * p + 3 * ax + d] = k.w;
+    } else if (lane < 24) {
+        if (lane < 21)
+            bc[3 * p + lane - 18] = k.first;
+        else
+            bf[3 * p + lane - 21] = k.first;
+    } else if (lane < 27) {
+        qh[3 * p + lane - 24] = x[lane - 24];
     }
 }
 
@@ -620,33 +809,18 @@ __global__ __launch_bounds__(256) void k_post(const PartArgs<T> a) {
     if (p >= a.np) return;
     const int lane = threadIdx.x & 63;
     const double qh[3] = {a.qh[3 * p], a.qh[3 * p + 1], a.qh[3 * p + 2]};
-    double sv[3] = {0, 0, 0}, sm[3] = {0, 0, 0};
-    for (int item = lane; item < 81; item += 64) {
-        const int ax = item / 27, pt = item % 27;
-        size_t i;
-        double w;
-        stencil_point(a.G, qh, ax + 1, pt, &i, &w);
-        const size_t j = plus_one(a.G, i, ax);
-        const double rf = a.G.rho0 + 0.5 * ((double)a.f[0][i] + (double)a.f[0][j]);
-        sv[ax] += w * ((double)a.f[1 + ax][i] / rf);
-        sm[ax] += w * rf;
-    }
-    double Vt[3], mf[3];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        Vt[ax] = wave_sum(sv[ax]);
-        mf[ax] = a.V * wave_sum(sm[ax]);
-    }
-    if (lane == 0) {
+    double Vt[3], sm[3];
+    wave_face_sums<T>(a.G, a.f, qh, Vt, sm);
+    if (lane < 3) {
+        const int ax = lane;
         const double me = a.me[p];
-        for (int ax = 0; ax < 3; ++ax) {
-            if (!(me + mf[ax] > 0.0)) a.flag[0] = 1;
-            const double u = a.u[3 * p + ax];
-            const double un = u + mf[ax] / (me + mf[ax]) * (Vt[ax] - u);
-            a.Vt[3 * p + ax] = un;  // u^{n+1}
-            a.du[3 * p + ax] = a.V * (un - Vt[ax]);
-            a.mf[3 * p + ax] = mf[ax];
-        }
+        const double mf = a.V * sm[ax];
+        if (!(me + mf > 0.0)) a.flag[0] = 1;
+        const double u = a.u[3 * p + ax];
+        const double un = u + mf / (me + mf) * (Vt[ax] - u);
+        a.Vt[3 * p + ax] = un;  // u^{n+1}
+        a.du[3 * p + ax] = a.V * (un - Vt[ax]);
+        a.mf[3 * p + ax] = mf;
     }
 }
 
@@ -658,19 +832,18 @@ __global__ __launch_bounds__(256) void k_final(const PartArgs<T> a) {
     const int lane = threadIdx.x & 63;
     const double qh[3] = {a.qh[3 * p], a.qh[3 * p + 1], a.qh[3 * p + 2]};
     double jv[3];
-    wave_velocity<T>(a.G, a.f, qh, jv);
-    if (lane == 0) {
-        for (int ax = 0; ax < 3; ++ax) {
-            const double q = a.q[3 * p + ax];
-            a.q[3 * p + ax] = wrap_pos(q + 0.5 * a.dt * (jv[ax] + a.jv_old[3 * p + ax]), a.L[ax]);
-            const double un = a.Vt[3 * p + ax];
-            const double F = a.F[3 * p + ax];
-            const double lam = a.me[p] * (un - a.u[3 * p + ax]) / a.dt - F;
-            a.sum_f[3 * p + ax] += -(F - a.fext[3 * p + ax]);
-            a.sum_l[3 * p + ax] += lam;
-            a.u[3 * p + ax] = un;
-            a.jv_new[3 * p + ax] = jv[ax];
-        }
+    wave_face_sums<T>(a.G, a.f, qh, jv, nullptr);
+    if (lane < 3) {
+        const int ax = lane;
+        const double q = a.q[3 * p + ax];
+        a.q[3 * p + ax] = wrap_pos(q + 0.5 * a.dt * (jv[ax] + a.jv_old[3 * p + ax]), a.L[ax]);
+        const double un = a.Vt[3 * p + ax];
+        const double F = a.F[3 * p + ax];
+        const double lam = a.me[p] * (un - a.u[3 * p + ax]) / a.dt - F;
+        a.sum_f[3 * p + ax] += -(F - a.fext[3 * p + ax]);
+        a.sum_l[3 * p + ax] += lam;
+        a.u[3 * p + ax] = un;
+        a.jv_new[3 * p + ax] = jv[ax];
     }
 }
 
@@ -682,9 +855,8 @@ __global__ __launch_bounds__(256) void k_init_u(const PartArgs<T> a) {
     const int lane = threadIdx.x & 63;
     const double q[3] = {a.q[3 * p], a.q[3 * p + 1], a.q[3 * p + 2]};
     double U[3];
-    wave_velocity<T>(a.G, a.f, q, U);
-    if (lane == 0)
-        for (int ax = 0; ax < 3; ++ax) a.u[3 * p + ax] = U[ax];
+    wave_face_sums<T>(a.G, a.f, q, U, nullptr);
+    if (lane < 3) a.u[3 * p + lane] = U[lane];
 }
 
 // Standalone J of a caller field.
@@ -697,35 +869,33 @@ __global__ __launch_bounds__(256) void k_interp(const Grid G, int np, const doub
     const double L[3] = {G.nx * G.h, G.ny * G.h, G.nz * G.h};
     const double qq[3] = {wrap_pos(q[3 * p], L[0]), wrap_pos(q[3 * p + 1], L[1]),
                           wrap_pos(q[3 * p + 2], L[2])};
-    double s = 0.0;
-    if (lane < 27) {
-        size_t i;
-        double w;
-        stencil_point(G, qq, kind, lane, &i, &w);
-        s = w * (double)field[i];
-    }
+    const WaveKernel k = wave_kernel(G, qq);
+    size_t i;
+    double w;
+    wave_point(G, k, kind, lane < 27 ? lane : 0, &i, &w);
+    double s = lane < 27 ? w * (double)field[i] : 0.0;
     s = wave_sum(s);
     if (lane == 0) out[p] = s;
 }
 
 // ---------------------------------------------------------------------------
-// Binning of particles into stage blocks (one workgroup).  A particle is
-// listed for every block whose cells, ring of halo cells or extra plane its
-// kernel points (cell- or face-centred, within [f-1, f+2] of f = floor(q/h)
-// per axis) can reach.  Lists are sorted by particle id.
+// Binning of particles into stage blocks.  A particle is listed for every
+// block whose cells, ring of halo cells or extra plane its kernel points
+// (within [f-1, f+2] of f = floor(q/h) per axis) can reach; each list is
+// sorted by the particle's first plane relative to the block (key) and id.
 // ---------------------------------------------------------------------------
 struct BinArgs {
-    int np, nx, ny, nz, gx, gy, gz, nblk;
+    int np, nx, ny, nz, gx, gy, gz, nblk, tz;
     double inv_h;
     const double *qh;
-    int32_t *count, *off, *cursor, *list;
+    int32_t *count, *off, *cursor, *list, *key;
 };
 
 // Distinct tile indices (tile size ts) touched by positions f-2 .. f+3.
 __device__ __forceinline__ int axis_tiles(int f, int n, int ts, int out[3]) {
     int cnt = 0;
     for (int s = f - 2; s <= f + 3; ++s) {
-        int t = ((s % n) + n) % n / ts;
+        const int t = ((s % n) + n) % n / ts;
         bool seen = false;
         for (int c = 0; c < cnt; ++c) seen |= out[c] == t;
         if (!seen && cnt < 3) out[cnt++] = t;
@@ -733,32 +903,38 @@ __device__ __forceinline__ int axis_tiles(int f, int n, int ts, int out[3]) {
     return cnt;
 }
 
-__device__ __forceinline__ int particle_blocks(const BinArgs &b, int p, int out[27]) {
+__device__ __forceinline__ int particle_blocks(const BinArgs &b, int p, int out[27], int keys[27]) {
     int tx[3], ty[3], tz[3];
     const double *q = b.qh + 3 * p;
+    const int fz = (int)floor(q[2] * b.inv_h);
     const int cx = axis_tiles((int)floor(q[0] * b.inv_h), b.nx, TX, tx);
     const int cy = axis_tiles((int)floor(q[1] * b.inv_h), b.ny, TY, ty);
-    const int cz = axis_tiles((int)floor(q[2] * b.inv_h), b.nz, TZ, tz);
+    const int cz = axis_tiles(fz, b.nz, b.tz, tz);
     int n = 0;
-    for (int k = 0; k < cz; ++k)
+    for (int k = 0; k < cz; ++k) {
+        const int z0 = tz[k] * b.tz;
+        const int key = (((fz - 1) - (z0 - 3)) % b.nz + b.nz) % b.nz;
         for (int j = 0; j < cy; ++j)
-            for (int i = 0; i < cx; ++i) out[n++] = (tz[k] * b.gy + ty[j]) * b.gx + tx[i];
+            for (int i = 0; i < cx; ++i) {
+                keys[n] = key;
+                out[n++] = (tz[k] * b.gy + ty[j]) * b.gx + tx[i];
+            }
+    }
     return n;
 }
 
-__global__ __launch_bounds__(1024) void k_bin(const BinArgs b) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int i = tid; i < b.nblk; i += nt) b.count[i] = 0;
-    __syncthreads();
-    for (int p = tid; p < b.np; p += nt) {
-        int bl[27];
-        const int n = particle_blocks(b, p, bl);
-        for (int c = 0; c < n; ++c) atomicAdd(&b.count[bl[c]], 1);
-    }
-    __threadfence_block();
-    __syncthreads();
-    // exclusive scan of count -> off (contiguous chunk per thread)
+__global__ __launch_bounds__(256) void k_bin_count(const BinArgs b) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= b.np) return;
+    int bl[27], ky[27];
+    const int n = particle_blocks(b, p, bl, ky);
+    for (int c = 0; c < n; ++c) atomicAdd(&b.count[bl[c]], 1);
+}
+
+// Exclusive scan of count into off (and cursor); re-zeroes count.
+__global__ __launch_bounds__(1024) void k_bin_scan(const BinArgs b) {
     __shared__ int32_t part[1024];
+    const int tid = threadIdx.x, nt = blockDim.x;
     const int chunk = (b.nblk + nt - 1) / nt;
     const int lo = min(tid * chunk, b.nblk), hi = min(lo + chunk, b.nblk);
     int s = 0;
@@ -773,99 +949,224 @@ __global__ __launch_bounds__(1024) void k_bin(const BinArgs b) {
     }
     int run = part[tid] - s;
     for (int i = lo; i < hi; ++i) {
+        const int c = b.count[i];
         b.off[i] = run;
         b.cursor[i] = run;
-        run += b.count[i];
+        b.count[i] = 0;
+        run += c;
     }
     if (tid == nt - 1) b.off[b.nblk] = part[nt - 1];
-    __threadfence_block();
-    __syncthreads();
-    for (int p = tid; p < b.np; p += nt) {
-        int bl[27];
-        const int n = particle_blocks(b, p, bl);
-        for (int c = 0; c < n; ++c) b.list[atomicAdd(&b.cursor[bl[c]], 1)] = p;
-    }
-    __threadfence_block();
-    __syncthreads();
-    for (int i = tid; i < b.nblk; i += nt) {
-        const int s0 = b.off[i], s1 = b.off[i + 1];
-        for (int m = s0 + 1; m < s1; ++m) {
-            const int v = b.list[m];
-            int j = m - 1;
-            while (j >= s0 && b.list[j] > v) {
-                b.list[j + 1] = b.list[j];
-                --j;
-            }
-            b.list[j + 1] = v;
-        }
+}
+
+__global__ __launch_bounds__(256) void k_bin_fill(const BinArgs b) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= b.np) return;
+    int bl[27], ky[27];
+    const int n = particle_blocks(b, p, bl, ky);
+    for (int c = 0; c < n; ++c) {
+        const int slot = atomicAdd(&b.cursor[bl[c]], 1);
+        b.list[slot] = p;
+        b.key[slot] = ky[c];
     }
 }
 
-// Owner-computes spreading onto faces (or cells) of the blocks that hold
-// candidates: field[c] += scale(i) * sum_p val_p w_p(i) / h^3, with
-// scale = rho_face of `drho` when drho is given (the momentum correction of
-// substep 6) and 1 otherwise.  Each grid point is written by one thread.
-template <typename T>
-struct SpreadArgs {
-    int nx, ny, nz;
-    double inv_h3, rho0;
-    const int32_t *blk_off, *blk_list, *bc, *bf;
-    const double *wc, *wf;
-    const double *val;   // val[vstride * p + c]
-    int vstride, ncomp, kind0;
-    T *fields[3];
-    const T *drho;
-};
+// One wave per block list: rank sort by (key, particle id) in LDS; lists
+// longer than the LDS buffer fall back to an insertion sort by lane 0.
+constexpr int SORT_CAP = 512;
+
+__global__ __launch_bounds__(64) void k_bin_sort(const BinArgs b) {
+    __shared__ int32_t sk[SORT_CAP], sp[SORT_CAP];
+    const int blk = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int s0 = b.off[blk], n = b.off[blk + 1] - s0;
+    if (n <= 1) return;
+    if (n <= SORT_CAP) {
+        for (int i = lane; i < n; i += 64) {
+            sk[i] = b.key[s0 + i];
+            sp[i] = b.list[s0 + i];
+        }
+        __syncthreads();
+        for (int i = lane; i < n; i += 64) {
+            const int ki = sk[i], pi = sp[i];
+            int rank = 0;
+            for (int j = 0; j < n; ++j) rank += (sk[j] < ki) || (sk[j] == ki && sp[j] < pi);
+            b.list[s0 + rank] = pi;
+            b.key[s0 + rank] = ki;
+        }
+        return;
+    }
+    if (lane != 0) return;
+    for (int m = s0 + 1; m < s0 + n; ++m) {
+        const int v = b.list[m], kv = b.key[m];
+        int j = m - 1;
+        while (j >= s0 && (b.key[j] > kv || (b.key[j] == kv && b.list[j] > v))) {
+            b.list[j + 1] = b.list[j];
+            b.key[j + 1] = b.key[j];
+            --j;
+        }
+        b.list[j + 1] = v;
+        b.key[j + 1] = kv;
+    }
+}
+
+// Sparse owner-computes updates of the grid near particles, one stage block
+// per workgroup.  Each block stages its candidate particles in LDS and
+// applies their contributions to its own grid points only, in list order:
+// candidates whose point boxes do not overlap run together, others one
+// after the other, so every point receives its sums in the same order on
+// every run (no float atomics).  Modes:
+//   SP_SPREAD : field += f_p w_p / h^3 (caller spreading, one location kind)
+//   SP_NOSLIP : g^a += rho_face V w_a (u^{n+1} - V~)^a / h^3 (substep 6)
+//   SP_STAGE  : g^a += b [-(dt/h) (P(i+a) - P(i)) + dt F^a w_a / h^3] with
+//               P = Omega w / h^3, the particle pressure and the spread
+//               external force of one RK stage (App. A, stage pressures).
+enum { SP_SPREAD = 0, SP_NOSLIP = 1, SP_STAGE = 2 };
 
 template <typename T>
-__global__ __launch_bounds__(STAGE_THREADS) void k_spread_binned(const SpreadArgs<T> a) {
+struct SparseArgs {
+    int nx, ny, nz, tz;
+    double inv_h3, rho0, b, dt_h, dt;
+    const int32_t *blk_off, *blk_list, *bc, *bf;
+    const double *wc, *wf;
+    const double *val;   // SPREAD: f[p]; NOSLIP: du[p][3]; STAGE: F[p][3]
+    const double *omega; // STAGE only
+    int kind;            // SPREAD only
+    T *fields[3];
+    const T *drho;       // NOSLIP only
+};
+
+constexpr int SP_CAP = 128;  // candidates staged in LDS at a time
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(STAGE_THREADS) void k_sparse(const SparseArgs<T> a) {
+    __shared__ int32_t s_bc[SP_CAP][3], s_bf[SP_CAP][3];
+    __shared__ double s_wc[SP_CAP][9], s_wf[SP_CAP][9], s_v[SP_CAP][4];
+    __shared__ int s_clash;
     const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     const int cb = a.blk_off[blk], ce = a.blk_off[blk + 1];
     if (cb == ce) return;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
-    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
-    const int x = x0 + lx, y = y0 + ly;
-    if (x >= nx || y >= ny) return;
-    const int z1 = min(z0 + TZ, nz);
     const int n[3] = {nx, ny, nz};
-    for (int z = z0; z < z1; ++z) {
-        const size_t g = ((size_t)z * ny + y) * nx + x;
-        const int pos[3] = {x, y, z};
-        for (int c = 0; c < a.ncomp; ++c) {
-            const int kind = a.kind0 + c;  // 0 cell, 1+a face a
-            double s = 0.0;
-            bool hit = false;
-            for (int ci = cb; ci < ce; ++ci) {
-                const int pid = a.blk_list[ci];
-                double w = 1.0;
-                bool in = true;
-                for (int ax = 0; ax < 3; ++ax) {
-                    const bool face = kind == ax + 1;
-                    int d = pos[ax] - (face ? a.bf[3 * pid + ax] : a.bc[3 * pid + ax]);
-                    if (d < 0) d += n[ax];
-                    if (d >= 3) {
-                        in = false;
-                        break;
-                    }
-                    w *= face ? a.wf[9 * pid + 3 * ax + d] : a.wc[9 * pid + 3 * ax + d];
-                }
-                if (in) {
-                    s += a.val[a.vstride * pid + c] * w;
-                    hit = true;
-                }
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * a.tz;
+    const int lo[3] = {x0, y0, z0};
+    const int wd[3] = {min(TX, nx - x0), min(TY, ny - y0), min(a.tz, nz - z0)};
+    const int tid = threadIdx.x;
+    constexpr int ncomp = MODE == SP_SPREAD ? 1 : 3;
+    constexpr int per_comp = MODE == SP_STAGE ? 36 : 27;
+    constexpr int per = ncomp * per_comp;
+    constexpr int group = STAGE_THREADS / per;
+
+    for (int c0 = cb; c0 < ce; c0 += SP_CAP) {
+        const int nc = min(SP_CAP, ce - c0);
+        __syncthreads();
+        for (int i = tid; i < nc; i += STAGE_THREADS) {
+            const int pid = a.blk_list[c0 + i];
+            for (int d = 0; d < 3; ++d) {
+                s_bc[i][d] = a.bc[3 * pid + d];
+                s_bf[i][d] = a.bf[3 * pid + d];
             }
-            if (hit) {
-                double scale = 1.0;
-                if (a.drho != nullptr && kind > 0) {
-                    const int ax = kind - 1;
-                    int nb[3] = {x, y, z};
-                    nb[ax] = nb[ax] + 1 == n[ax] ? 0 : nb[ax] + 1;
-                    const size_t j = ((size_t)nb[2] * ny + nb[1]) * nx + nb[0];
-                    scale = a.rho0 + 0.5 * ((double)a.drho[g] + (double)a.drho[j]);
+            for (int d = 0; d < 9; ++d) {
+                s_wc[i][d] = a.wc[9 * pid + d];
+                s_wf[i][d] = a.wf[9 * pid + d];
+            }
+            if (MODE == SP_SPREAD) {
+                s_v[i][0] = a.val[pid];
+            } else {
+                for (int d = 0; d < 3; ++d) s_v[i][d] = a.val[3 * pid + d];
+                s_v[i][3] = MODE == SP_STAGE ? a.omega[pid] : 0.0;
+            }
+        }
+        __syncthreads();
+        for (int g0 = 0; g0 < nc; g0 += group) {
+            const int g1 = min(g0 + group, nc);
+            // overlap test of the group's point boxes [bc-1, bc+2] per axis
+            if (tid == 0) {
+                int clash = 0;
+                for (int i = g0; i < g1 && !clash; ++i)
+                    for (int j = i + 1; j < g1 && !clash; ++j) {
+                        bool all = true;
+                        for (int ax = 0; ax < 3; ++ax) {
+                            int d = s_bc[i][ax] - s_bc[j][ax];
+                            if (d < 0) d = -d;
+                            d = min(d, n[ax] - d);
+                            all = all && d <= 3;
+                        }
+                        clash = all;
+                    }
+                s_clash = clash;
+            }
+            __syncthreads();
+            const bool clash = s_clash != 0;
+            const int rounds = clash ? g1 - g0 : 1;
+            for (int r = 0; r < rounds; ++r) {
+                const int ci = clash ? g0 + r : g0 + tid / per;
+                const bool active = clash ? tid < per : (tid < (g1 - g0) * per);
+                if (active) {
+                    const int item = tid % per;
+                    const int comp = item / per_comp, pt = item % per_comp;
+                    const int kind = MODE == SP_SPREAD ? a.kind : 1 + comp;
+                    const int fa = kind - 1;  // face axis, -1 for cells
+                    // point index along each axis relative to the box start
+                    int d[3];
+                    if (MODE == SP_STAGE) {
+                        int rr = pt;  // extents 4 along the face axis, 3 along the others
+                        for (int ax = 0; ax < 3; ++ax) {
+                            const int e = ax == fa ? 4 : 3;
+                            d[ax] = rr % e;
+                            rr /= e;
+                        }
+                    } else {
+                        d[0] = pt % 3;
+                        d[1] = (pt / 3) % 3;
+                        d[2] = pt / 9;
+                    }
+                    int pos[3];
+                    bool in = true;
+                    for (int ax = 0; ax < 3; ++ax) {
+                        int start;
+                        if (MODE == SP_STAGE)
+                            start = s_bc[ci][ax] - (ax == fa ? 1 : 0);
+                        else
+                            start = ax == fa ? s_bf[ci][ax] : s_bc[ci][ax];
+                        pos[ax] = wrap(start + d[ax], n[ax]);
+                        in = in && pos[ax] >= lo[ax] && pos[ax] < lo[ax] + wd[ax];
+                    }
+                    if (in) {
+                        const size_t g = ((size_t)pos[2] * ny + pos[1]) * nx + pos[0];
+                        // weight of the cell (face == -1) or face stencil at pos
+                        auto weight = [&](const int p[3], int face) {
+                            double w = 1.0;
+                            for (int ax = 0; ax < 3; ++ax) {
+                                const bool f = ax == face;
+                                int o = p[ax] - (f ? s_bf[ci][ax] : s_bc[ci][ax]);
+                                if (o < 0) o += n[ax];
+                                if (o >= 3) return 0.0;
+                                w *= f ? s_wf[ci][3 * ax + o] : s_wc[ci][3 * ax + o];
+                            }
+                            return w;
+                        };
+                        double add;
+                        if (MODE == SP_SPREAD) {
+                            add = s_v[ci][0] * weight(pos, fa) * a.inv_h3;
+                        } else if (MODE == SP_NOSLIP) {
+                            int nb[3] = {pos[0], pos[1], pos[2]};
+                            nb[fa] = nb[fa] + 1 == n[fa] ? 0 : nb[fa] + 1;
+                            const size_t j = ((size_t)nb[2] * ny + nb[1]) * nx + nb[0];
+                            const double rf = a.rho0 + 0.5 * ((double)a.drho[g] + (double)a.drho[j]);
+                            add = rf * s_v[ci][comp] * weight(pos, fa) * a.inv_h3;
+                        } else {
+                            int nb[3] = {pos[0], pos[1], pos[2]};
+                            nb[fa] = nb[fa] + 1 == n[fa] ? 0 : nb[fa] + 1;
+                            const double om = s_v[ci][3];
+                            const double dP = om * (weight(nb, -1) - weight(pos, -1)) * a.inv_h3;
+                            const double fw = s_v[ci][comp] * weight(pos, fa) * a.inv_h3;
+                            add = a.b * (-a.dt_h * dP + a.dt * fw);
+                        }
+                        T *fld = a.fields[comp];
+                        fld[g] = (T)((double)fld[g] + add);
+                    }
                 }
-                T *fld = a.fields[c];
-                fld[g] = (T)((double)fld[g] + scale * s * a.inv_h3);
+                __syncthreads();
             }
         }
     }
@@ -903,10 +1204,7 @@ PartArgs<T> part_args(ic_ctx *c, void *const f[4]) {
     PartArgs<T> a{};
     const ic_params &p = c->p;
     a.G = Grid{p.nx, p.ny, p.nz, p.h, 1.0 / p.h, p.rho0};
-    for (int i = 0; i < 4; ++i) {
-        a.f[i] = (const T *)f[i];
-        a.fw[i] = (T *)f[i];
-    }
+    for (int i = 0; i < 4; ++i) a.f[i] = (const T *)f[i];
     a.np = c->np;
     a.dt = p.dt;
     a.V = 8.0 * p.h * p.h * p.h;
@@ -932,16 +1230,42 @@ BinArgs bin_args(ic_ctx *c, int np, const double *qh) {
     b.gy = c->nblk[1];
     b.gz = c->nblk[2];
     b.nblk = b.gx * b.gy * b.gz;
+    b.tz = c->tz;
     b.inv_h = 1.0 / c->p.h;
     b.qh = qh;
     b.count = c->ws.blk_count;
     b.off = c->ws.blk_off;
     b.cursor = c->ws.blk_cursor;
     b.list = c->ws.blk_list;
+    b.key = c->ws.blk_key;
     return b;
 }
 
 inline unsigned wave_blocks(int n) { return (unsigned)((n * 64 + 255) / 256); }
+inline unsigned thread_blocks(int n) { return (unsigned)((n + 255) / 256); }
+
+void launch_binning(ic_ctx *c, int np, const double *qh) {
+    const BinArgs b = bin_args(c, np, qh);
+    hipLaunchKernelGGL(k_bin_count, dim3(thread_blocks(np)), dim3(256), 0, c->stream, b);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, c->stream, b);
+    hipLaunchKernelGGL(k_bin_fill, dim3(thread_blocks(np)), dim3(256), 0, c->stream, b);
+    hipLaunchKernelGGL(k_bin_sort, dim3(b.nblk), dim3(64), 0, c->stream, b);
+}
+
+template <typename T>
+SparseArgs<T> sparse_args(ic_ctx *c) {
+    const ic_params &p = c->p;
+    const Workspace &w = c->ws;
+    SparseArgs<T> sa{};
+    sa.nx = p.nx; sa.ny = p.ny; sa.nz = p.nz; sa.tz = c->tz;
+    sa.inv_h3 = 1.0 / (p.h * p.h * p.h);
+    sa.rho0 = p.rho0;
+    sa.dt_h = p.dt / p.h;
+    sa.dt = p.dt;
+    sa.blk_off = w.blk_off; sa.blk_list = w.blk_list;
+    sa.bc = w.pk.bc; sa.bf = w.pk.bf; sa.wc = w.pk.wc; sa.wf = w.pk.wf;
+    return sa;
+}
 
 template <typename T>
 hipError_t step_impl(ic_ctx *c) {
@@ -950,16 +1274,18 @@ hipError_t step_impl(ic_ctx *c) {
     const Workspace &w = c->ws;
     void *U[4] = {c->f[0], c->f[1], c->f[2], c->f[3]};
     const dim3 grid(c->nblk[0], c->nblk[1], c->nblk[2]);
+    const unsigned nblk_all = (unsigned)(c->nblk[0] * c->nblk[1] * c->nblk[2]);
     const int np = c->np;
     PartArgs<T> pa = part_args<T>(c, U);
 
     if (np > 0) {
         hipLaunchKernelGGL(k_pre<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa);
-        hipLaunchKernelGGL(k_bin, dim3(1), dim3(1024), 0, s, bin_args(c, np, w.qh));
+        launch_binning(c, np, w.qh);
     }
 
     StageArgs<T> a{};
-    a.nx = p.nx; a.ny = p.ny; a.nz = p.nz;
+    a.nx = p.nx; a.ny = p.ny; a.nz = p.nz; a.tz = c->tz;
+    a.gx = c->nblk[0]; a.gy = c->nblk[1]; a.gz = c->nblk[2];
     a.rho0 = (T)p.rho0;
     a.cf2 = (T)(p.cf * p.cf);
     a.eta = (T)p.eta;
@@ -967,31 +1293,32 @@ hipError_t step_impl(ic_ctx *c) {
     a.inv_h = (T)(1.0 / p.h);
     a.dt_h = (T)(p.dt / p.h);
     a.dt = (T)p.dt;
-    const double amp = 1.0 / sqrt(p.h * p.h * p.h * p.dt);
-    const double an = sqrt(2.0 * p.eta * p.kT);
-    const double bt = sqrt(p.zeta * p.kT / 3.0) - an / 3.0;
-    a.sd = (T)(amp * an * sqrt(2.0));
-    a.st = (T)(amp * bt * sqrt(2.0));
-    a.so = (T)(amp * an);
-    a.nk = NoiseKey{(uint32_t)(p.seed & 0xFFFFFFFFu), (uint32_t)(p.seed >> 32),
-                    (uint32_t)(c->step & 0xFFFFFFFF), p.replica};
-    a.np = np;
-    a.blk_off = w.blk_off;
-    a.blk_list = w.blk_list;
-    a.bc = w.pk.bc; a.bf = w.pk.bf; a.wc = w.pk.wc; a.wf = w.pk.wf;
-    a.omega = w.omega;
-    a.F = w.F;
-    a.inv_h3 = 1.0 / (p.h * p.h * p.h);
+    const bool noise = p.kT > 0.0;
+    if (noise) {
+        NoiseArgs<T> na{};
+        for (int i = 0; i < 9; ++i) na.out[i] = (T *)w.N[i];
+        na.nx = p.nx; na.ny = p.ny; na.nz = p.nz; na.tz = c->tz;
+        na.gx = c->nblk[0]; na.gy = c->nblk[1]; na.gz = c->nblk[2];
+        const double amp = 1.0 / sqrt(p.h * p.h * p.h * p.dt);
+        const double an = sqrt(2.0 * p.eta * p.kT);
+        const double bt = sqrt(p.zeta * p.kT / 3.0) - an / 3.0;
+        na.dt_h = (T)(p.dt / p.h);
+        na.sd = (T)(amp * an * sqrt(2.0));
+        na.st = (T)(amp * bt * sqrt(2.0));
+        na.so = (T)(amp * an);
+        na.s3 = (T)sqrt(3.0);
+        na.nk = NoiseKey{(uint32_t)(p.seed & 0xFFFFFFFFu), (uint32_t)(p.seed >> 32),
+                         (uint32_t)(c->step & 0xFFFFFFFF), p.replica};
+        hipLaunchKernelGGL(noise_kernel<T>, dim3(nblk_all), dim3(STAGE_THREADS), 0, s, na);
+    }
     a.nmodes = c->forcing.nmodes;
     a.prof = w.prof;
     a.pstride = c->prof_stride;
     for (int m = 0; m < a.nmodes; ++m) a.maxis[m] = c->forcing.modes[m].axis;
 
-    const bool noise = p.kT > 0.0;
     const double tn = (double)c->step * p.dt;
     const double tst[3] = {tn, tn + p.dt, tn + 0.5 * p.dt};
     const double ra[3] = {0.0, 0.75, 1.0 / 3.0}, rb[3] = {1.0, 0.25, 2.0 / 3.0};
-    const double wB[3] = {-sqrt(3.0), sqrt(3.0), 0.0};
     void *const A[4] = {w.A[0], w.A[1], w.A[2], w.A[3]};
     void *const B[4] = {w.B[0], w.B[1], w.B[2], w.B[3]};
     void *const *src[3] = {U, A, B};
@@ -1007,14 +1334,14 @@ hipError_t step_impl(ic_ctx *c) {
         }
         a.ra = (T)ra[st];
         a.rb = (T)rb[st];
-        a.wB = (T)wB[st];
+        for (int i = 0; i < 3; ++i) a.noise[i] = noise ? (const T *)w.N[3 * st + i] : nullptr;
         for (int m = 0; m < a.nmodes; ++m) {
             const ic_mode &md = c->forcing.modes[m];
-            a.mamp[m] = md.amp * sin(md.omega * tst[st] + md.phase);
+            a.mamp[m] = (T)(md.amp * sin(md.omega * tst[st] + md.phase));
         }
         hipEvent_t e0 = prof_event(c), e1 = prof_event(c);
-        if (e0) hipEventRecord(e0, s);
-#define IC_STAGE(S, N) hipLaunchKernelGGL((stage_kernel<T, S, N>), grid, dim3(STAGE_THREADS), 0, s, a)
+        if (e0) (void)hipEventRecord(e0, s);
+#define IC_STAGE(S, N) hipLaunchKernelGGL((stage_kernel<T, S, N>), dim3(nblk_all), dim3(STAGE_THREADS), 0, s, a)
         if (noise) {
             if (st == 0) IC_STAGE(0, true); else if (st == 1) IC_STAGE(1, true); else IC_STAGE(2, true);
         } else {
@@ -1022,26 +1349,26 @@ hipError_t step_impl(ic_ctx *c) {
         }
 #undef IC_STAGE
         if (e1) {
-            hipEventRecord(e1, s);
+            (void)hipEventRecord(e1, s);
             prof_push(c, e0, e1);
+        }
+        if (np > 0) {
+            SparseArgs<T> sa = sparse_args<T>(c);
+            sa.b = rb[st];
+            sa.val = w.F;
+            sa.omega = w.omega;
+            for (int i = 0; i < 3; ++i) sa.fields[i] = (T *)dst[st][1 + i];
+            hipLaunchKernelGGL((k_sparse<T, SP_STAGE>), grid, dim3(STAGE_THREADS), 0, s, sa);
         }
     }
 
     if (np > 0) {
         hipLaunchKernelGGL(k_post<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa);
-        SpreadArgs<T> sa{};
-        sa.nx = p.nx; sa.ny = p.ny; sa.nz = p.nz;
-        sa.inv_h3 = 1.0 / (p.h * p.h * p.h);
-        sa.rho0 = p.rho0;
-        sa.blk_off = w.blk_off; sa.blk_list = w.blk_list;
-        sa.bc = w.pk.bc; sa.bf = w.pk.bf; sa.wc = w.pk.wc; sa.wf = w.pk.wf;
+        SparseArgs<T> sa = sparse_args<T>(c);
         sa.val = w.du;
-        sa.vstride = 3;
-        sa.ncomp = 3;
-        sa.kind0 = 1;
         for (int i = 0; i < 3; ++i) sa.fields[i] = (T *)U[1 + i];
         sa.drho = (const T *)U[0];
-        hipLaunchKernelGGL(k_spread_binned<T>, grid, dim3(STAGE_THREADS), 0, s, sa);
+        hipLaunchKernelGGL((k_sparse<T, SP_NOSLIP>), grid, dim3(STAGE_THREADS), 0, s, sa);
         hipLaunchKernelGGL(k_final<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa);
     }
     return hipGetLastError();
@@ -1062,23 +1389,15 @@ hipError_t spread_impl(ic_ctx *c, int n, const double *q, const double *f, int k
     const ic_params &p = c->p;
     const Workspace &w = c->ws;
     const Grid G{p.nx, p.ny, p.nz, p.h, 1.0 / p.h, p.rho0};
-    hipLaunchKernelGGL(k_weights, dim3((n + 255) / 256), dim3(256), 0, c->stream, G, n, q, w.qh,
+    hipLaunchKernelGGL(k_weights, dim3(wave_blocks(n)), dim3(256), 0, c->stream, G, n, q, w.qh,
                        w.pk.bc, w.pk.bf, w.pk.wc, w.pk.wf);
-    hipLaunchKernelGGL(k_bin, dim3(1), dim3(1024), 0, c->stream, bin_args(c, n, w.qh));
-    SpreadArgs<T> sa{};
-    sa.nx = p.nx; sa.ny = p.ny; sa.nz = p.nz;
-    sa.inv_h3 = 1.0 / (p.h * p.h * p.h);
-    sa.rho0 = p.rho0;
-    sa.blk_off = w.blk_off; sa.blk_list = w.blk_list;
-    sa.bc = w.pk.bc; sa.bf = w.pk.bf; sa.wc = w.pk.wc; sa.wf = w.pk.wf;
+    launch_binning(c, n, w.qh);
+    SparseArgs<T> sa = sparse_args<T>(c);
     sa.val = f;
-    sa.vstride = 1;
-    sa.ncomp = 1;
-    sa.kind0 = kind;
+    sa.kind = kind;
     sa.fields[0] = (T *)field;
-    sa.drho = nullptr;
     const dim3 grid(c->nblk[0], c->nblk[1], c->nblk[2]);
-    hipLaunchKernelGGL(k_spread_binned<T>, grid, dim3(STAGE_THREADS), 0, c->stream, sa);
+    hipLaunchKernelGGL((k_sparse<T, SP_SPREAD>), grid, dim3(STAGE_THREADS), 0, c->stream, sa);
     return hipGetLastError();
 }
 

@@ -13,10 +13,10 @@
 namespace ic {
 
 // Stage-kernel tile: TX cells along x (one half-wave row each), TY rows along
-// y, marching over up to TZ planes along z.  One thread per (x, y) column.
+// y, marching over up to tz planes along z (tz chosen per grid, see
+// choose_tz).  One thread per (x, y) column.
 constexpr int TX = 32;
-constexpr int TY = 8;
-constexpr int TZ = 32;
+constexpr int TY = 16;
 constexpr int STAGE_THREADS = TX * TY;
 // Largest number of stencil blocks one particle's influence box can touch
 // (at most 3 tiles per axis).
@@ -36,13 +36,14 @@ struct PartKernel {
 struct Workspace {
     void *A[4];          // stage buffer U~ (drho, gx, gy, gz)
     void *B[4];          // stage buffer U^{n+1/2}
+    void *N[9];          // stochastic increments of the three stages (x, y, z each); kT > 0 only
     // persistent particle state, [N][3] or [N]
     double *q, *u, *me, *eps, *ks, *qeq, *fext;
     // per-step particle data
     double *qh, *jv_old, *F, *Vt, *du, *mf, *omega, *jv_new;
     PartKernel pk;
     // binning of particles into stage blocks
-    int32_t *blk_count, *blk_off, *blk_cursor, *blk_list;
+    int32_t *blk_count, *blk_off, *blk_cursor, *blk_list, *blk_key;
     // accumulators
     double *sum_f, *sum_l;
     // forcing profiles [IC_MAX_MODES][pmax]
@@ -71,6 +72,7 @@ struct ic_ctx {
     int64_t nsamples;
     ic::Forcing forcing;
     int nblk[3];
+    int tz;
     int prof_stride;
     std::string err;
     // stage-kernel timing (ic_profile)
@@ -84,6 +86,7 @@ struct ic_ctx {
 namespace ic {
 
 size_t workspace_bytes(const ic_params &p, size_t *offsets_out = nullptr);
+int choose_tz(const ic_params &p);
 void carve_workspace(const ic_params &p, char *base, Workspace &ws);
 int nblocks_total(const ic_params &p);
 
