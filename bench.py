@@ -14,22 +14,36 @@ of the fields as deviations from rho0, FP64 particle state and
 accumulators); the FP64 run of the same workload is reported beside it.
 
 roofline: the dominant kernel is the fluid-stage kernel (three launches per
-step).  Its algorithmic HBM traffic is 32 words per cell-update (stage 1:
-read 4 + write 4; stages 2 and 3: read 4 + 4 + write 4), i.e. 128 B (FP32)
-or 256 B (FP64); achieved = those bytes / the summed duration of the stage
-launches, measured with HIP events on the stream the kernels run on, over
-the timed region.  Peak = 8 TB/s.
+step).  Its algorithmic HBM traffic is 32 words per cell-update over the
+three launches (stage 1: read 4 + write 4; stages 2 and 3: read 4 + 4 +
+write 4), i.e. 128 B (FP32) or 256 B (FP64) per cell-update; achieved = those
+bytes / the summed duration of the stage launches, measured with HIP events
+recorded on the stream the kernels run on, over the timed region.
+Peak = 8 TB/s.  traffic = HBM bytes per stage launch from rocprofv3
+FETCH_SIZE and WRITE_SIZE counters, each scaled by what the same counter
+reads for a plain 1 GiB device copy; it is read from the committed counter
+summary and reported only while the kernel source still matches the one the
+counters were taken on.
 
-cpu_baseline: the FP64 numpy oracle (as it stands) timed for one step on a
-256 x 256 x 64 slab of the same workload (2500 particles at the same
-density), on the host.
+cpu_baseline: the FP64 numpy oracle (as it stands) timed for one full step of
+the same workload on the host (about 15 s of CPU work; the particles start at
+rest instead of at J v, which does not change the work done).
+
+Helper modes (they serve the profiles kept beside this file):
+  --copy-probe              1 GiB device-to-device copies (counter calibration
+                            and the achievable copy bandwidth)
+  --stats-summary CSV       condense a rocprofv3 --stats kernel table
+  --pmc-summary F W CF CW   condense FETCH_SIZE / WRITE_SIZE passes of the bench
+                            (F, W) and of the copy probe (CF, CW)
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
 import json
-import math
 import os
+import re
 import sys
 import time
 
@@ -41,10 +55,20 @@ if ROOT not in sys.path:
 
 METRIC = "cell-updates/s + % HBM roofline at 256^3/1e4 particles; FP32 vs FP64; adjoint cost"
 HBM_PEAK_GBS = 8000.0
+WORDS_PER_CELL_UPDATE = 32          # over the three stage launches of one step
+STAGES = 3
+KERNEL_SRC = os.path.join(ROOT, "paper_1307_0702_amd", "csrc", "ic_device.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "stage_kernel_256cube_1e4p_pmc.txt")
+COPY_BYTES = 1 << 30
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
 
 
 def make_workload(name):
@@ -92,7 +116,7 @@ def run_gpu(w, prec, steps, warmup):
     ic.ic_profile(sim.ctx, 0)
     ncell = fl.nx * fl.ny * fl.nz
     esz = 4 if prec == "fp32" else 8
-    bytes_alg = 32 * esz * ncell * steps
+    bytes_alg = WORDS_PER_CELL_UPDATE * esz * ncell * steps
     c = sim.conserved()
     finite = bool(np.all(np.isfinite(c)))
     res = dict(
@@ -104,6 +128,7 @@ def run_gpu(w, prec, steps, warmup):
         stage_launches=launches,
         stage_achieved_gbs=bytes_alg / (stage_ms * 1e-3) / 1e9 if stage_ms > 0 else None,
         step_achieved_gbs=bytes_alg / wall / 1e9,
+        alg_bytes_per_launch=bytes_alg / max(launches, 1),
         finite=finite,
     )
     log(f"[bench] {prec}: {res['ms_per_step']:.3f} ms/step, stage kernel "
@@ -113,50 +138,163 @@ def run_gpu(w, prec, steps, warmup):
     return res
 
 
-def cpu_baseline(w_full):
-    """One oracle step on a 256 x 256 x 64 slab of the workload."""
-    from oracle import ic_oracle as O
-    from paper_1307_0702_amd import workloads as W
+def measured_traffic(prec):
+    """HBM bytes per stage launch from the committed counter summary, or None
+    when the summary is missing or was taken on another kernel source."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None, "no counter summary"
+    vals = {}
+    with open(PMC_SUMMARY) as f:
+        for line in f:
+            m = re.match(r"^(\w+):\s*(\S+)", line)
+            if m:
+                vals[m.group(1)] = m.group(2)
+    if vals.get("source_sha256") != kernel_source_sha():
+        return None, "kernel changed since the counters were taken"
+    key = f"traffic_bytes_per_stage_launch_{prec}"
+    if key not in vals:
+        return None, "no counters for " + prec
+    return float(vals[key]), "rocprofv3 FETCH_SIZE x%s + WRITE_SIZE x%s" % (
+        vals.get("fetch_scale", "?"), vals.get("write_scale", "?"))
 
-    fl = W.Fluid(w_full.fluid.nx, w_full.fluid.ny, 64, kT=w_full.fluid.kT, seed=w_full.fluid.seed)
-    npart = int(round(w_full.particles.n * fl.nz / w_full.fluid.nz))
-    p = W.split_contrast_particles(fl, npart, seed=fl.seed, ks=10.0)
-    mode, _ = W.modal_drive(fl, 1e-2)
-    drho, g = W.standing_wave_fields(fl, 1e-2, omega=mode.omega)
+
+def roofline(r, prec):
+    traffic, note = measured_traffic(prec)
+    esz = 4 if prec == "fp32" else 8
+    ach = r["stage_achieved_gbs"]
+    return dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=(ach / HBM_PEAK_GBS) if ach else None, traffic=traffic,
+                kernel="stage_kernel", launches_per_step=STAGES,
+                alg_bytes_per_launch=r["alg_bytes_per_launch"],
+                bytes_per_cell_update=WORDS_PER_CELL_UPDATE * esz,
+                traffic_source=note,
+                step_frac=r["step_achieved_gbs"] / HBM_PEAK_GBS)
+
+
+def cpu_baseline(w):
+    """One FP64 oracle step of the full workload (same fields, particles,
+    drive and noise key) on the host."""
+    from oracle import ic_oracle as O
+
+    fl, p = w.fluid, w.particles
     eps = O.eps_from_kappa_ratio(fl.cf, p.kappa_ratio)
-    st = dict(drho=drho, g=[g[0], g[1], g[2]], n=0, q=p.q, u=np.zeros((npart, 3)), me=p.me,
-              eps=eps, ks=p.ks, qeq=p.qeq, fext=p.fext)
-    prm = fl.as_dict()
-    log(f"[bench] cpu baseline: oracle, 1 step on {fl.nx}x{fl.ny}x{fl.nz}, {npart} particles")
+    st = dict(drho=w.drho.copy(), g=[c.copy() for c in w.g], n=0, q=p.q.copy(),
+              u=np.zeros((p.n, 3)), me=p.me, eps=eps, ks=p.ks, qeq=p.qeq, fext=p.fext)
+    log(f"[bench] cpu baseline: oracle, 1 step on {fl.nx}x{fl.ny}x{fl.nz}, {p.n} particles")
     c0 = time.process_time()
     t0 = time.perf_counter()
-    O.ic_step(st, prm, [mode.as_dict()])
+    O.ic_step(st, fl.as_dict(), [m.as_dict() for m in w.modes])
     wall = time.perf_counter() - t0
     cpu = time.process_time() - c0
     ncell = fl.nx * fl.ny * fl.nz
     log(f"[bench] cpu baseline: {wall:.1f} s")
     return dict(value=ncell / wall, unit="cell-updates/s", cores=max(1, int(round(cpu / wall))),
                 kind="oracle",
-                sample=f"1 FP64 oracle step on a {fl.nx}x{fl.ny}x{fl.nz} slab of the workload "
-                       f"({npart} particles, same density, kT and drive); {wall:.1f} s wall")
+                sample=f"1 FP64 oracle step (numpy, as it stands) of the full workload: "
+                       f"{fl.nx}x{fl.ny}x{fl.nz} cells, {p.n} particles; {wall:.1f} s wall")
+
+
+def copy_probe():
+    import torch
+    n = COPY_BYTES // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps(dict(copy_bytes=COPY_BYTES, ms=dt * 1e3,
+                          gbs_read_plus_write=2 * COPY_BYTES / dt / 1e9)), flush=True)
+
+
+def _short(name):
+    name = re.sub(r"\(ic::\(anonymous namespace\)::\w+(<\w+>)?\)", "", name)
+    name = name.replace("ic::(anonymous namespace)::", "").replace("void ", "")
+    return name[:60]
+
+
+def stats_summary(path):
+    rows = list(csv.DictReader(open(path)))
+    print("%-60s %7s %12s %8s" % ("kernel", "calls", "avg_us", "pct"))
+    for r in rows[:24]:
+        print("%-60s %7s %12.1f %8s" % (_short(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3,
+                                       r["Percentage"]))
+
+
+def _pmc(dirname):
+    per = {}
+    for fn in os.listdir(dirname):
+        if fn.endswith("counter_collection.csv"):
+            for r in csv.DictReader(open(os.path.join(dirname, fn))):
+                per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return per
+
+
+def pmc_summary(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir):
+    kib = 1024.0
+
+    def copy_reading(d):
+        vals = [v for k, vs in _pmc(d).items() if "copyBuffer" in k for v in vs]
+        big = [v for v in vals if v * kib > COPY_BYTES / 8]
+        return float(np.median(big))
+
+    cf, cw = copy_reading(cal_fetch_dir), copy_reading(cal_write_dir)
+    fs, ws = COPY_BYTES / (cf * kib), COPY_BYTES / (cw * kib)
+    print(f"copy_probe_fetch_kib: {cf:.1f}")
+    print(f"copy_probe_write_kib: {cw:.1f}")
+    print(f"fetch_scale: {fs:.4f}")
+    print(f"write_scale: {ws:.4f}")
+    print(f"source_sha256: {kernel_source_sha()}")
+    F, Wr = _pmc(fetch_dir), _pmc(write_dir)
+    print("%-44s %6s %12s %12s %14s" % ("kernel", "n", "FETCH_KiB", "WRITE_KiB", "bytes/launch"))
+    stage = {"float": [], "double": []}
+    for k in sorted(F, key=lambda s: -np.mean(F[s])):
+        if k not in Wr:
+            continue
+        f, wv = float(np.mean(F[k])), float(np.mean(Wr[k]))
+        tb = (f * fs + wv * ws) * kib
+        print("%-44s %6d %12.1f %12.1f %14.4g" % (_short(k)[:44], len(F[k]), f, wv, tb))
+        m = re.search(r"stage_kernel<(float|double), (\d)", k)
+        if m:
+            stage[m.group(1)].append((len(F[k]), tb))
+    for t, prec in (("float", "fp32"), ("double", "fp64")):
+        if stage[t]:
+            n = sum(c for c, _ in stage[t])
+            avg = sum(c * b for c, b in stage[t]) / n
+            print(f"traffic_bytes_per_stage_launch_{prec}: {avg:.6g}")
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="paper-scale-256")
     ap.add_argument("--prec", choices=["fp32", "fp64", "both"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--stats-summary", metavar="CSV")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"))
     args = ap.parse_args()
+    if args.stats_summary:
+        return stats_summary(args.stats_summary)
+    if args.pmc_summary:
+        return pmc_summary(*args.pmc_summary)
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is a "
-              "single-GPU build, see the design notes for how it would shard.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the IC step here "
+              "is a single-GPU build; the design notes describe how it would shard.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        return copy_probe()
     log(f"[bench] building inputs for {args.workload}")
     w = make_workload(args.workload)
     fl = w.fluid
@@ -166,10 +304,6 @@ def main():
         res[prec] = run_gpu(w, prec, args.steps, args.warmup)
     main_prec = precs[0]
     r = res[main_prec]
-    esz = 4 if main_prec == "fp32" else 8
-    roof = dict(bound="hbm", achieved=r["stage_achieved_gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=(r["stage_achieved_gbs"] / HBM_PEAK_GBS) if r["stage_achieved_gbs"] else None,
-                traffic=None, kernel="stage_kernel", bytes_per_cell_update=32 * esz)
     out = dict(
         metric=METRIC,
         value=r["cell_updates_per_s"],
@@ -186,15 +320,12 @@ def main():
         config=dict(workload=w.name, grid=[fl.nx, fl.ny, fl.nz], particles=w.particles.n,
                     kT=fl.kT, dt=fl.dt, storage="fields as deviations from rho0; particles FP64"),
         particle_updates_per_s=r["particle_updates_per_s"],
-        roofline=roof,
+        roofline=roofline(r, main_prec),
     )
     if "fp64" in res and main_prec != "fp64":
         r64 = res["fp64"]
         out["fp64"] = dict(value=r64["cell_updates_per_s"], ms_per_step=r64["ms_per_step"],
-                           roofline=dict(bound="hbm", achieved=r64["stage_achieved_gbs"],
-                                         peak=HBM_PEAK_GBS, unit="GB/s",
-                                         frac=r64["stage_achieved_gbs"] / HBM_PEAK_GBS,
-                                         bytes_per_cell_update=256))
+                           roofline=roofline(r64, "fp64"))
         out["speedup_fp32_over_fp64"] = r["cell_updates_per_s"] / r64["cell_updates_per_s"]
     out["finite"] = all(x["finite"] for x in res.values())
     if not args.no_cpu_baseline:
