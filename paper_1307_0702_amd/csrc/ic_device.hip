@@ -20,6 +20,8 @@
 // results are bitwise reproducible.
 #include <math.h>
 
+#include <type_traits>
+
 #include "ic_internal.h"
 
 namespace ic {
@@ -173,6 +175,7 @@ struct StageArgs {
     const T *un[4];   // U^n (stages 2 and 3)
     T *out[4];
     int nx, ny, nz, tz, gx, gy, gz;
+    uint32_t fbytes;  // bytes of one field (< 2^32)
     T rho0, cf2, eta, lam, inv_h, dt_h, dt, ra, rb;
     const T *noise[3]; // stochastic increment of this stage (x, y, z), NOISE only
     // imposed pressure: sum_m mamp[m] * prof[m][coord(maxis[m])]
@@ -189,6 +192,36 @@ constexpr int PS = PX * PY;
 
 __device__ __forceinline__ int lidx(int lx, int ly) { return (ly + 1) * PX + (lx + 1); }
 
+// Raw buffer access: a 32-bit per-thread byte offset inside a plane (VGPR)
+// plus a uniform plane offset (SGPR), so that loads and stores need no
+// per-access 64-bit address arithmetic.  Flags word of the gfx9 family.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
+                                             0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                              uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                uint32_t soff) {
+    return __builtin_bit_cast(double,
+                              __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                       uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                       uint32_t soff) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+}
+
 // Imposed pressure at cell (x, y, z).  The particle pressure S Omega and the
 // spread force S F are added after the sweep (k_sparse, stage mode): both
 // enter the stage output linearly.
@@ -203,20 +236,26 @@ __device__ __forceinline__ T ext_pressure(const StageArgs<T> &a, int x, int y, i
     return s;
 }
 
+// One RK stage over a tile of TX x TY columns, marching over planes k of
+// [z0, z1).  LDS holds only plane k: momentum and velocity on the region
+// [-1, W] x [-1, Wy], density of planes k and k+1 on [-1, W+1] x [-1, Wy+1]
+// (two alternating buffers) and the six x/y fluxes of plane k.  Values of
+// plane k+1 that plane k needs (g and v at the same column) come from the
+// registers that also commit plane k+1, and the zz flux of plane k+1 is
+// taken one iteration later, so the z-momentum of plane k is written in
+// iteration k+1.  Each thread owns one column; waves 0-3 also own one side
+// each of the momentum ring (+x column, -x column, +y row, -y row, computing
+// the fluxes the tile's own faces need there) and wave 4 the rest of the
+// density ring.  Register sets for planes k+1 and k+2 alternate, so every
+// load is issued one iteration before its use.
 template <typename T, int STAGE, bool NOISE>
-__global__ __launch_bounds__(STAGE_THREADS) void stage_kernel(const StageArgs<T> a) {
-    // Rotating plane buffers.  With four density, three momentum, two
-    // (vx, vy) / three (vz) velocity planes, the update of plane k and the
-    // commit of plane k+2 touch disjoint buffers, so each plane needs only
-    // two barriers.
-    __shared__ T s_rho[4][PS];
-    __shared__ T s_g[3][3][PS];
-    __shared__ T s_vx[2][PS], s_vy[2][PS], s_vz[3][PS];
-    __shared__ T s_fl[6][PS];  // Pxx, Pyy, Pxy, Pyx, Pzx, Pzy at the current plane
+__global__ __launch_bounds__(STAGE_THREADS)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void stage_kernel(const StageArgs<T> a) {
+    __shared__ T s_G[3][PS], s_V[3][PS], s_P[2][PS], s_F[6][PS];
 
     const int nx = a.nx, ny = a.ny, nz = a.nz, tz = a.tz;
-    const int plane = nx * ny;
-    const int tid = threadIdx.x;
+    const uint32_t pbytes = (uint32_t)nx * (uint32_t)ny * (uint32_t)sizeof(T);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     // Workgroups go to the 8 XCDs round-robin; give each XCD a contiguous run
     // of tiles (x fastest) so tiles sharing halo lines share one L2.
     int bx, by, bz;
@@ -228,254 +267,295 @@ __global__ __launch_bounds__(STAGE_THREADS) void stage_kernel(const StageArgs<T>
         by = (t / a.gx) % a.gy;
         bz = t / (a.gx * a.gy);
     }
-    const int x0 = bx * TX, y0 = by * TY, z0 = bz * tz;
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * tz;   // z0 is even (tz is)
     const int W = min(TX, nx - x0), Wy = min(TY, ny - y0), z1 = min(z0 + tz, nz);
-    const int lx = tid % TX, ly = tid / TX;
-    const bool own = lx < W && ly < Wy;
-    const int xo = x0 + lx, yo = y0 + ly;
-    const int li = lidx(lx, ly);
-    const int own_xy = own ? yo * nx + xo : 0;
     const T rho0 = a.rho0, half = (T)0.5, quarter = (T)0.25;
 
-    // Load slots (fixed for the whole march): density region
-    // [-1, W+1] x [-1, Wy+1], momentum/velocity region [-1, W] x [-1, Wy].
-    const int wr = W + 3, nrr = wr * (Wy + 3);
-    const int wg = W + 2, nrg = wg * (Wy + 2);
-    int r_l[2], r_xy[2], g_l[2], g_xy[2];
-    bool r_ok[2], g_ok[2];
+    __amdgpu_buffer_rsrc_t rin[4], run[4], rnn[3], rout[4];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        const int i = tid + s * STAGE_THREADS;
-        r_ok[s] = i < nrr;
-        const int ir = r_ok[s] ? i : 0;
-        const int rx = ir % wr - 1, ry = ir / wr - 1;
-        r_l[s] = lidx(rx, ry);
-        r_xy[s] = wrap(y0 + ry, ny) * nx + wrap(x0 + rx, nx);
-        g_ok[s] = i < nrg;
-        const int ig = g_ok[s] ? i : 0;
-        const int gxx = ig % wg - 1, gyy = ig / wg - 1;
-        g_l[s] = lidx(gxx, gyy);
-        g_xy[s] = wrap(y0 + gyy, ny) * nx + wrap(x0 + gxx, nx);
+    for (int c = 0; c < 4; ++c) {
+        rin[c] = make_rsrc(a.in[c], a.fbytes);
+        rout[c] = make_rsrc(a.out[c], a.fbytes);
+        if (STAGE != 0) run[c] = make_rsrc(a.un[c], a.fbytes);
     }
-    // Halo flux items: wave 0 takes the +x column (xx) and +y row (yy), wave 1
-    // the -x column (yx, zx) and -y row (xy, zy), so each wave draws one kind
-    // of noise subset.
-    int h_type = -1, h_x = 0, h_y = 0;
-    {
-        const int i = tid < 64 ? tid : tid - 64;
-        if (tid < 128 && i < Wy + W) {
-            if (tid < 64) {
-                if (i < Wy) { h_type = 0; h_x = W; h_y = i; }
-                else { h_type = 1; h_x = i - Wy; h_y = Wy; }
-            } else {
-                if (i < Wy) { h_type = 2; h_x = -1; h_y = i; }
-                else { h_type = 3; h_x = i - Wy; h_y = -1; }
-            }
-        }
+    if (NOISE) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rnn[c] = make_rsrc(a.noise[c], a.fbytes);
     }
-    const int h_l = lidx(h_x, h_y);
-    const int h_gx = wrap(x0 + h_x, nx), h_gy = wrap(y0 + h_y, ny);
-    const int h_xy = h_gy * nx + h_gx;
+    auto soff = [&](int p) -> uint32_t { return (uint32_t)wrap(p, nz) * pbytes; };
 
-    // Register prefetch: density of plane p+1 on the density slots, momentum
-    // of plane p and density of plane p+1 on the momentum slots.
-    T pr[2] = {0, 0}, pg[2][3] = {{0, 0, 0}, {0, 0, 0}}, pz[2] = {0, 0};
-    auto prefetch = [&](int p) {
-        const int zg = wrap(p, nz) * plane, zr = wrap(p + 1, nz) * plane;
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            if (r_ok[s]) pr[s] = a.in[0][zr + r_xy[s]];
-            if (g_ok[s]) {
-                pg[s][0] = a.in[1][zg + g_xy[s]];
-                pg[s][1] = a.in[2][zg + g_xy[s]];
-                pg[s][2] = a.in[3][zg + g_xy[s]];
-                pz[s] = a.in[0][zr + g_xy[s]];
-            }
+    // own column
+    const int lx = tid % TX, ly = tid / TX;
+    const bool own = lx < W && ly < Wy;
+    const int lo = lidx(lx, ly);
+    const int xo = x0 + lx, yo = y0 + ly;
+    const uint32_t vo = own ? (uint32_t)(yo * nx + xo) * (uint32_t)sizeof(T) : 0u;
+    // momentum ring (waves 0-3) and the rest of the density ring (wave 4)
+    bool r1 = false, r1f = false, r2 = false;
+    int r1x = 0, r1y = 0, r2x = 0, r2y = 0;
+    if (wave < 2) {
+        if (lane < Wy + 2) {
+            r1 = true;
+            r1x = wave == 0 ? W : -1;
+            r1y = lane - 1;
+            r1f = lane >= 1 && lane <= Wy;
         }
-    };
-    // Plane buffers of the march, rotated once per plane.  Slot names are
-    // relative to the plane k being updated.
-    T *rb[4] = {s_rho[0], s_rho[1], s_rho[2], s_rho[3]};        // k-1 .. k+2
-    T *gb[3] = {s_g[0][0], s_g[1][0], s_g[2][0]};               // k, k+1, k+2
-    T *vxb[2] = {s_vx[0], s_vx[1]}, *vyb[2] = {s_vy[0], s_vy[1]};  // k, k+1
-    T *vzb[3] = {s_vz[0], s_vz[1], s_vz[2]};                     // k-1, k, k+1
-    // Writes density of plane p+1 into rw, momentum of plane p into gw and
-    // v = g / rho_face of plane p (density of plane p in r) into vxw/vyw/vzw.
-    auto commit = [&](T *rw, const T *r, T *gw, T *vxw, T *vyw, T *vzw) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            if (r_ok[s]) rw[r_l[s]] = pr[s];
-            if (g_ok[s]) {
-                const int l = g_l[s];
-                gw[l] = pg[s][0];
-                gw[PS + l] = pg[s][1];
-                gw[2 * PS + l] = pg[s][2];
-                vxw[l] = pg[s][0] * fast_rcp<T>(rho0 + half * (r[l] + r[l + 1]));
-                vyw[l] = pg[s][1] * fast_rcp<T>(rho0 + half * (r[l] + r[l + PX]));
-                vzw[l] = pg[s][2] * fast_rcp<T>(rho0 + half * (r[l] + pz[s]));
-            }
+    } else if (wave < 4) {
+        if (lane < W) {
+            r1 = true;
+            r1f = true;
+            r1x = lane;
+            r1y = wave == 2 ? Wy : -1;
         }
+    } else if (wave == 4) {
+        if (lane < Wy + 3) {
+            r2 = true;
+            r2x = W + 1;
+            r2y = lane - 1;
+        } else if (lane < Wy + W + 5) {
+            r2 = true;
+            r2x = lane - (Wy + 3) - 1;
+            r2y = Wy + 1;
+        }
+    }
+    const int l1 = lidx(r1x, r1y), l2 = lidx(r2x, r2y);
+    const int g1x = wrap(x0 + r1x, nx), g1y = wrap(y0 + r1y, ny);
+    const uint32_t v1 = r1 ? (uint32_t)(g1y * nx + g1x) * (uint32_t)sizeof(T) : 0u;
+    const uint32_t v2 =
+        r2 ? (uint32_t)(wrap(y0 + r2y, ny) * nx + wrap(x0 + r2x, nx)) * (uint32_t)sizeof(T) : 0u;
+
+    // Register set for plane p: momentum of p and density of p+1 at the own
+    // column and the ring position, and density of p+1 on the density ring.
+    struct Set {
+        T g[3], rn, g1[3], rn1, rn2;
     };
-    T un[4] = {0, 0, 0, 0}, nn[3] = {0, 0, 0};
-    auto prefetch_un = [&](int p) {
-        if (own && p < z1) {
-            const int g = p * plane + own_xy;
+    auto load_set = [&](Set &S, int p) {
+        const uint32_t sg = soff(p), sr = soff(p + 1);
+        if (own) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) S.g[c] = bload<T>(rin[1 + c], vo, sg);
+            S.rn = bload<T>(rin[0], vo, sr);
+        }
+        if (r1) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) S.g1[c] = bload<T>(rin[1 + c], v1, sg);
+            S.rn1 = bload<T>(rin[0], v1, sr);
+        }
+        if (r2) S.rn2 = bload<T>(rin[0], v2, sr);
+    };
+    Set SO, SE;   // used by odd / even iterations k (planes k+1 even / odd)
+
+    // v = g / rho_face at a column with density r (plane p), its +x and +y
+    // neighbours and density rz of plane p+1 above it
+    auto vel = [&](const T g[3], T r, T rxp, T ryp, T rz, T v[3]) {
+        v[0] = g[0] * fast_rcp<T>(rho0 + half * (r + rxp));
+        v[1] = g[1] * fast_rcp<T>(rho0 + half * (r + ryp));
+        v[2] = g[2] * fast_rcp<T>(rho0 + half * (r + rz));
+    };
+
+    // ---- prologue: plane z0-1 into G/V, density z0-1 and z0 into P
+    {
+        const uint32_t sr = soff(z0 - 1);
+        if (own) s_P[1][lo] = bload<T>(rin[0], vo, sr);
+        if (r1) s_P[1][l1] = bload<T>(rin[0], v1, sr);
+        if (r2) s_P[1][l2] = bload<T>(rin[0], v2, sr);
+    }
+    load_set(SE, z0 - 1);
+    __syncthreads();
+    {
+        const T *P = s_P[1];
+        if (own) {
+            T v[3];
+            vel(SE.g, P[lo], P[lo + 1], P[lo + PX], SE.rn, v);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                s_G[c][lo] = SE.g[c];
+                s_V[c][lo] = v[c];
+            }
+            s_P[0][lo] = SE.rn;
+        }
+        if (r1) {
+            T v[3];
+            vel(SE.g1, P[l1], P[l1 + 1], P[l1 + PX], SE.rn1, v);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                s_G[c][l1] = SE.g1[c];
+                s_V[c][l1] = v[c];
+            }
+            s_P[0][l1] = SE.rn1;
+        }
+        if (r2) s_P[0][l2] = SE.rn2;
+    }
+    load_set(SO, z0);
+    load_set(SE, z0 + 1);
+    __syncthreads();
+
+    // carried values
+    T vzm = 0, gzm = 0;           // own column: vz, gz of plane k-1
+    T vzm1 = 0;                   // ring position: vz of plane k-1
+    T Pzz_m = 0, Pxz_m = 0, Pyz_m = 0;   // own column: zz flux at k-1, xz/yz at k-1/2
+    T lag_d = 0, lag_u = 0, lag_n = 0;   // z-momentum of plane k-1 waiting for Pzz(k)
+    const T dth = a.dt_h;
+
+    auto fin_gz = [&](int kz, T Pzz_k) {
+        // z-momentum of plane kz = k-1, now that the zz flux of plane k is known
+        const T d = lag_d - dth * (Pzz_k - Pzz_m);
+        const T v = STAGE == 0 ? lag_u + d : a.ra * lag_n + a.rb * (lag_u + d);
+        bstore(v, rout[3], vo, soff(kz));
+    };
+
+    // One plane.  ODD: parity of k (fixes the buffer roles); PREP: k = z0-1,
+    // which only prepares carried values.
+    auto iteration = [&](auto odd_c, auto prep_c, const int k, Set &S) {
+        constexpr bool ODD = decltype(odd_c)::value, PREP = decltype(prep_c)::value;
+        const T *Pk = s_P[ODD ? 1 : 0];     // density of plane k
+        const T *P1 = s_P[ODD ? 0 : 1];     // density of plane k+1
+        T *Pw = s_P[ODD ? 1 : 0];           // receives density of plane k+2
+        const T *gx = s_G[0], *gy = s_G[1], *gz = s_G[2];
+        const T *vx = s_V[0], *vy = s_V[1], *vz = s_V[2];
+        const int zk = k;                   // k in [z0-1, z1)
+        // ---- phase B: velocities of plane k+1, fluxes of plane k
+        T vn[3] = {0, 0, 0}, vn1[3] = {0, 0, 0};
+        T un[4] = {0, 0, 0, 0}, nn[3] = {0, 0, 0}, mflux = 0, Pxz = 0, Pyz = 0;
+        if (!PREP && own) {
+            const uint32_t su = soff(zk);
             if (STAGE != 0) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) un[c] = a.un[c][g];
+                for (int c = 0; c < 4; ++c) un[c] = bload<T>(run[c], vo, su);
             }
             if (NOISE) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) nn[c] = a.noise[c][g];
+                for (int c = 0; c < 3; ++c) nn[c] = bload<T>(rnn[c], vo, su);
             }
         }
-    };
-
-    // ---- prologue.  Iteration k = z0-1 only prepares carried values; in
-    // its slot naming density k-1 (= z0-2) is never used.
-    {
-        const int zr = wrap(z0 - 1, nz) * plane;
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-            if (r_ok[s]) rb[1][r_l[s]] = a.in[0][zr + r_xy[s]];     // density z0-1 (slot k)
-    }
-    prefetch(z0 - 1);
-    __syncthreads();
-    commit(rb[2], rb[1], gb[0], vxb[0], vyb[0], vzb[1]);           // density z0, plane z0-1
-    prefetch(z0);
-    prefetch_un(z0);
-    __syncthreads();
-
-    T Pzz_cur = 0, Pxz_prev = 0, Pyz_prev = 0, gz_prev = 0, pex_cur = 0;
-
-    for (int k = z0 - 1; k < z1; ++k) {
-        const bool prep = (k == z0 - 1);
-        // ---- phase A: plane k+1 into LDS, then start loading plane k+2
-        commit(rb[3], rb[2], gb[1], vxb[1], vyb[1], vzb[2]);
-        const T un_cur[4] = {un[0], un[1], un[2], un[3]};
-        const T nn_cur[3] = {nn[0], nn[1], nn[2]};
-        if (k + 2 <= z1) prefetch(k + 2);
-        prefetch_un(k + 1);
-        __syncthreads();
-
-        const T *rk = rb[1], *rk1 = rb[2];
-        const T *gx = gb[0], *gy = gb[0] + PS, *gz = gb[0] + 2 * PS;
-        const T *gx1 = gb[1], *gy1 = gb[1] + PS, *gz1 = gb[1] + 2 * PS;
-        const T *vx = vxb[0], *vy = vyb[0], *vz = vzb[1];
-        const T *vx1 = vxb[1], *vy1 = vyb[1], *vz1 = vzb[2];
-        const T *vzm = vzb[0];
-        const int zk = wrap(k, nz), zk1 = wrap(k + 1, nz);
-
-        // ---- phase B: fluxes
-        T Pzz_next = 0, Pxz_cur = 0, Pyz_cur = 0, pex_next = 0;
         if (own) {
-            // centre flux zz at plane k+1
-            pex_next = ext_pressure(a, xo, yo, zk1);
-            const int l = li;
-            const T div1 = ((vx1[l] - vx1[l - 1]) + (vy1[l] - vy1[l - PX]) + (vz1[l] - vz[l])) *
-                           a.inv_h;
-            T pzz = a.cf2 * rk1[l] + pex_next + quarter * (gz1[l] + gz[l]) * (vz1[l] + vz[l]) -
-                    (2 * a.eta * (vz1[l] - vz[l]) * a.inv_h + a.lam * div1);
-            Pzz_next = pzz;
-            // edge fluxes along z at plane k (own column only)
-            const T viz_x = a.eta * ((vx1[l] - vx[l]) + (vz[l + 1] - vz[l])) * a.inv_h;
-            const T viz_y = a.eta * ((vy1[l] - vy[l]) + (vz[l + PX] - vz[l])) * a.inv_h;
-            Pxz_cur = quarter * (gx[l] + gx1[l]) * (vz[l] + vz[l + 1]) - viz_x;
-            Pyz_cur = quarter * (gy[l] + gy1[l]) * (vz[l] + vz[l + PX]) - viz_y;
-            if (!prep) {
-                const T pi = a.cf2 * rk[l] + pex_cur;
-                const T div = ((vx[l] - vx[l - 1]) + (vy[l] - vy[l - PX]) + (vz[l] - vzm[l])) *
-                              a.inv_h;
-                T pxx = pi + quarter * (gx[l] + gx[l - 1]) * (vx[l] + vx[l - 1]) -
-                        (2 * a.eta * (vx[l] - vx[l - 1]) * a.inv_h + a.lam * div);
-                T pyy = pi + quarter * (gy[l] + gy[l - PX]) * (vy[l] + vy[l - PX]) -
-                        (2 * a.eta * (vy[l] - vy[l - PX]) * a.inv_h + a.lam * div);
+            const int l = lo;
+            vel(S.g, P1[l], P1[l + 1], P1[l + PX], S.rn, vn);
+            const T viz_x = a.eta * ((vn[0] - vx[l]) + (vz[l + 1] - vz[l])) * a.inv_h;
+            const T viz_y = a.eta * ((vn[1] - vy[l]) + (vz[l + PX] - vz[l])) * a.inv_h;
+            Pxz = quarter * (gx[l] + S.g[0]) * (vz[l] + vz[l + 1]) - viz_x;
+            Pyz = quarter * (gy[l] + S.g[1]) * (vz[l] + vz[l + PX]) - viz_y;
+            if (!PREP) {
+                const T pi = a.cf2 * Pk[l] + ext_pressure(a, xo, yo, wrap(zk, nz));
+                const T dvx = vx[l] - vx[l - 1], dvy = vy[l] - vy[l - PX], dvz = vz[l] - vzm;
+                const T ldiv = a.lam * ((dvx + dvy + dvz) * a.inv_h);
+                const T Pzz = pi + quarter * (gz[l] + gzm) * (vz[l] + vzm) -
+                              (2 * a.eta * dvz * a.inv_h + ldiv);
+                if (k > z0) fin_gz(k - 1, Pzz);
+                Pzz_m = Pzz;
+                const T pxx = pi + quarter * (gx[l] + gx[l - 1]) * (vx[l] + vx[l - 1]) -
+                              (2 * a.eta * dvx * a.inv_h + ldiv);
+                const T pyy = pi + quarter * (gy[l] + gy[l - PX]) * (vy[l] + vy[l - PX]) -
+                              (2 * a.eta * dvy * a.inv_h + ldiv);
                 const T vxy = a.eta * ((vx[l + PX] - vx[l]) + (vy[l + 1] - vy[l])) * a.inv_h;
-                T pxy = quarter * (gx[l] + gx[l + PX]) * (vy[l] + vy[l + 1]) - vxy;
-                T pyx = quarter * (gy[l] + gy[l + 1]) * (vx[l] + vx[l + PX]) - vxy;
-                T pzx = quarter * (gz[l] + gz[l + 1]) * (vx[l] + vx1[l]) - viz_x;
-                T pzy = quarter * (gz[l] + gz[l + PX]) * (vy[l] + vy1[l]) - viz_y;
-                s_fl[0][l] = pxx;
-                s_fl[1][l] = pyy;
-                s_fl[2][l] = pxy;
-                s_fl[3][l] = pyx;
-                s_fl[4][l] = pzx;
-                s_fl[5][l] = pzy;
+                s_F[0][l] = pxx;
+                s_F[1][l] = pyy;
+                s_F[2][l] = quarter * (gx[l] + gx[l + PX]) * (vy[l] + vy[l + 1]) - vxy;
+                s_F[3][l] = quarter * (gy[l] + gy[l + 1]) * (vx[l] + vx[l + PX]) - vxy;
+                s_F[4][l] = quarter * (gz[l] + gz[l + 1]) * (vx[l] + vn[0]) - viz_x;
+                s_F[5][l] = quarter * (gz[l] + gz[l + PX]) * (vy[l] + vn[1]) - viz_y;
+                mflux = (gx[l] - gx[l - 1]) + (gy[l] - gy[l - PX]) + (gz[l] - gzm);
             }
+            vzm = vz[l];
+            gzm = gz[l];
         }
-        if (!prep && h_type >= 0) {
-            const int l = h_l;
-            if (h_type <= 1) {
-                const T pi = a.cf2 * rk[l] + ext_pressure(a, h_gx, h_gy, zk);
-                const T div = ((vx[l] - vx[l - 1]) + (vy[l] - vy[l - PX]) + (vz[l] - vzm[l])) *
-                              a.inv_h;
-                if (h_type == 0)
-                    s_fl[0][l] = pi + quarter * (gx[l] + gx[l - 1]) * (vx[l] + vx[l - 1]) -
-                                 (2 * a.eta * (vx[l] - vx[l - 1]) * a.inv_h + a.lam * div);
-                else
-                    s_fl[1][l] = pi + quarter * (gy[l] + gy[l - PX]) * (vy[l] + vy[l - PX]) -
-                                 (2 * a.eta * (vy[l] - vy[l - PX]) * a.inv_h + a.lam * div);
-            } else {
-                const T vxy = a.eta * ((vx[l + PX] - vx[l]) + (vy[l + 1] - vy[l])) * a.inv_h;
-                if (h_type == 2) {
-                    const T viz_x = a.eta * ((vx1[l] - vx[l]) + (vz[l + 1] - vz[l])) * a.inv_h;
-                    s_fl[3][l] = quarter * (gy[l] + gy[l + 1]) * (vx[l] + vx[l + PX]) - vxy;
-                    s_fl[4][l] = quarter * (gz[l] + gz[l + 1]) * (vx[l] + vx1[l]) - viz_x;
-                } else {
-                    const T viz_y = a.eta * ((vy1[l] - vy[l]) + (vz[l + PX] - vz[l])) * a.inv_h;
-                    s_fl[2][l] = quarter * (gx[l] + gx[l + PX]) * (vy[l] + vy[l + 1]) - vxy;
-                    s_fl[5][l] = quarter * (gz[l] + gz[l + PX]) * (vy[l] + vy1[l]) - viz_y;
+        if (r1) {
+            const int l = l1;
+            vel(S.g1, P1[l], P1[l + 1], P1[l + PX], S.rn1, vn1);
+            if (!PREP && r1f) {
+                if (wave == 0) {            // +x column: centre flux xx
+                    const T pi = a.cf2 * Pk[l] + ext_pressure(a, g1x, g1y, wrap(zk, nz));
+                    const T dvx = vx[l] - vx[l - 1];
+                    const T div = (dvx + (vy[l] - vy[l - PX]) + (vz[l] - vzm1)) * a.inv_h;
+                    s_F[0][l] = pi + quarter * (gx[l] + gx[l - 1]) * (vx[l] + vx[l - 1]) -
+                                (2 * a.eta * dvx * a.inv_h + a.lam * div);
+                } else if (wave == 2) {     // +y row: centre flux yy
+                    const T pi = a.cf2 * Pk[l] + ext_pressure(a, g1x, g1y, wrap(zk, nz));
+                    const T dvy = vy[l] - vy[l - PX];
+                    const T div = ((vx[l] - vx[l - 1]) + dvy + (vz[l] - vzm1)) * a.inv_h;
+                    s_F[1][l] = pi + quarter * (gy[l] + gy[l - PX]) * (vy[l] + vy[l - PX]) -
+                                (2 * a.eta * dvy * a.inv_h + a.lam * div);
+                } else if (wave == 1) {     // -x column: edge fluxes yx, zx
+                    const T vxy = a.eta * ((vx[l + PX] - vx[l]) + (vy[l + 1] - vy[l])) * a.inv_h;
+                    const T viz_x = a.eta * ((vn1[0] - vx[l]) + (vz[l + 1] - vz[l])) * a.inv_h;
+                    s_F[3][l] = quarter * (gy[l] + gy[l + 1]) * (vx[l] + vx[l + PX]) - vxy;
+                    s_F[4][l] = quarter * (gz[l] + gz[l + 1]) * (vx[l] + vn1[0]) - viz_x;
+                } else {                    // -y row: edge fluxes xy, zy
+                    const T vxy = a.eta * ((vx[l + PX] - vx[l]) + (vy[l + 1] - vy[l])) * a.inv_h;
+                    const T viz_y = a.eta * ((vn1[1] - vy[l]) + (vz[l + PX] - vz[l])) * a.inv_h;
+                    s_F[2][l] = quarter * (gx[l] + gx[l + PX]) * (vy[l] + vy[l + 1]) - vxy;
+                    s_F[5][l] = quarter * (gz[l] + gz[l + PX]) * (vy[l] + vn1[1]) - viz_y;
                 }
             }
+            vzm1 = vz[l];
         }
         __syncthreads();
 
-        // ---- phase C: update of plane k (no barrier after it: the next
-        // commit writes buffers this phase does not read)
-        if (!prep && own) {
-            const int l = li;
-            const T drho = -a.dt_h * ((gx[l] - gx[l - 1]) + (gy[l] - gy[l - PX]) + (gz[l] - gz_prev));
-            const T dgx = -a.dt_h * ((s_fl[0][l + 1] - s_fl[0][l]) + (s_fl[2][l] - s_fl[2][l - PX]) +
-                                     (Pxz_cur - Pxz_prev));
-            const T dgy = -a.dt_h * ((s_fl[1][l + PX] - s_fl[1][l]) + (s_fl[3][l] - s_fl[3][l - 1]) +
-                                     (Pyz_cur - Pyz_prev));
-            const T dgz = -a.dt_h * ((Pzz_next - Pzz_cur) + (s_fl[4][l] - s_fl[4][l - 1]) +
-                                     (s_fl[5][l] - s_fl[5][l - PX]));
-            const int g = zk * plane + own_xy;
-            const T us[4] = {rk[l], gx[l], gy[l], gz[l]};
-            T d[4] = {drho, dgx, dgy, dgz};
-            if (NOISE) {
-                d[1] += nn_cur[0];
-                d[2] += nn_cur[1];
-                d[3] += nn_cur[2];
-            }
+        // ---- phase X: update of plane k (z-momentum: of plane k-1, done
+        // above), then plane k+1 into G/V and density of plane k+2 into P
+        if (own) {
+            if (!PREP) {
+                const int l = lo;
+                // own column of plane k: only this thread writes it below
+                const T us[4] = {Pk[l], s_G[0][l], s_G[1][l], s_G[2][l]};
+                T d[3];
+                d[0] = -dth * mflux;
+                d[1] = -dth * ((s_F[0][l + 1] - s_F[0][l]) + (s_F[2][l] - s_F[2][l - PX]) + (Pxz - Pxz_m));
+                d[2] = -dth * ((s_F[1][l + PX] - s_F[1][l]) + (s_F[3][l] - s_F[3][l - 1]) + (Pyz - Pyz_m));
+                lag_d = -dth * ((s_F[4][l] - s_F[4][l - 1]) + (s_F[5][l] - s_F[5][l - PX]));
+                if (NOISE) {
+                    d[1] += nn[0];
+                    d[2] += nn[1];
+                    lag_d += nn[2];
+                }
+                lag_u = us[3];
+                lag_n = un[3];
+                const uint32_t so = soff(zk);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                T v;
-                if (STAGE == 0)
-                    v = us[c] + d[c];
-                else
-                    v = a.ra * un_cur[c] + a.rb * (us[c] + d[c]);
-                a.out[c][g] = v;
+                for (int c = 0; c < 3; ++c) {
+                    const T v = STAGE == 0 ? us[c] + d[c] : a.ra * un[c] + a.rb * (us[c] + d[c]);
+                    bstore(v, rout[c], vo, so);
+                }
             }
+            Pxz_m = Pxz;
+            Pyz_m = Pyz;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                s_G[c][lo] = S.g[c];
+                s_V[c][lo] = vn[c];
+            }
+            Pw[lo] = S.rn;
         }
-        if (own) gz_prev = gz[li];
-        Pzz_cur = Pzz_next;
-        Pxz_prev = Pxz_cur;
-        Pyz_prev = Pyz_cur;
-        pex_cur = pex_next;
-        // rotate: density k-1 <- k <- k+1 <- k+2, momentum k <- k+1 <- k+2,
-        // velocities k-1 <- k <- k+1
-        {
-            T *t = rb[0];
-            rb[0] = rb[1]; rb[1] = rb[2]; rb[2] = rb[3]; rb[3] = t;
-            t = gb[0];
-            gb[0] = gb[1]; gb[1] = gb[2]; gb[2] = t;
-            t = vxb[0]; vxb[0] = vxb[1]; vxb[1] = t;
-            t = vyb[0]; vyb[0] = vyb[1]; vyb[1] = t;
-            t = vzb[0];
-            vzb[0] = vzb[1]; vzb[1] = vzb[2]; vzb[2] = t;
+        if (r1) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                s_G[c][l1] = S.g1[c];
+                s_V[c][l1] = vn1[c];
+            }
+            Pw[l1] = S.rn1;
         }
+        if (r2) Pw[l2] = S.rn2;
+        if (k + 3 <= z1) load_set(S, k + 3);
+        __syncthreads();
+    };
+    using T1 = std::integral_constant<bool, true>;
+    using F0 = std::integral_constant<bool, false>;
+    iteration(T1{}, T1{}, z0 - 1, SO);
+    for (int k = z0; k < z1; k += 2) {
+        iteration(F0{}, F0{}, k, SE);
+        if (k + 1 < z1) iteration(T1{}, F0{}, k + 1, SO);
+    }
+    // ---- tail: zz flux of plane z1 finishes the z-momentum of plane z1-1
+    if (own) {
+        const int l = lo;
+        const T *Pz = s_P[z1 & 1];
+        const T *gz = s_G[2], *vx = s_V[0], *vy = s_V[1], *vz = s_V[2];
+        const T pi = a.cf2 * Pz[l] + ext_pressure(a, xo, yo, wrap(z1, nz));
+        const T dvz = vz[l] - vzm;
+        const T div = ((vx[l] - vx[l - 1]) + (vy[l] - vy[l - PX]) + dvz) * a.inv_h;
+        const T Pzz = pi + quarter * (gz[l] + gzm) * (vz[l] + vzm) -
+                      (2 * a.eta * dvz * a.inv_h + a.lam * div);
+        fin_gz(z1 - 1, Pzz);
     }
 }
 
@@ -1293,6 +1373,7 @@ hipError_t step_impl(ic_ctx *c) {
     a.inv_h = (T)(1.0 / p.h);
     a.dt_h = (T)(p.dt / p.h);
     a.dt = (T)p.dt;
+    a.fbytes = (uint32_t)((size_t)p.nx * p.ny * p.nz * sizeof(T));
     const bool noise = p.kT > 0.0;
     if (noise) {
         NoiseArgs<T> na{};
