@@ -87,7 +87,8 @@ typedef struct ic_ctx ic_ctx;
 
 /* Validates p and creates a context bound to HIP stream `stream` (NULL =
  * default stream) on the current device.  Host only; allocates no device
- * memory.  IC_E_ARG for sizes < 4 per side, non-positive h, rho0, cf, dt,
+ * memory.  IC_E_ARG for sizes < 4 per side, a field of 4 GiB or more
+ * (nx ny nz times the element size), non-positive h, rho0, cf, dt,
  * negative viscosities or kT; IC_E_UNSTABLE when cf dt/h > 0.5 or
  * (4 eta/3 + zeta)/rho0 * dt/h^2 > 0.2 (reading: the SSP-RK3 stability
  * region on the imaginary and real axes for the largest staggered-grid

@@ -121,6 +121,9 @@ int check_params(const ic_params *p, ic_ctx *c) {
     if ((double)p->nx * p->ny * p->nz > 2147483647.0)
         return fail(c, IC_E_ARG, "grid larger than 2^31 cells");
     if (p->prec != IC_FP32 && p->prec != IC_FP64) return fail(c, IC_E_ARG, "prec must be IC_FP32 or IC_FP64");
+    // the stage kernel addresses a field with 32-bit byte offsets
+    if ((double)p->nx * p->ny * p->nz * (p->prec == IC_FP64 ? 8.0 : 4.0) >= 4294967296.0)
+        return fail(c, IC_E_ARG, "one field must be smaller than 4 GiB");
     if (!(p->h > 0) || !(p->rho0 > 0) || !(p->cf > 0) || !(p->dt > 0))
         return fail(c, IC_E_ARG, "h, rho0, cf and dt must be positive");
     if (!(p->eta >= 0) || !(p->zeta >= 0) || !(p->kT >= 0))

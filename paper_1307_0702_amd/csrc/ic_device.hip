@@ -968,6 +968,7 @@ struct BinArgs {
     int np, nx, ny, nz, gx, gy, gz, nblk, tz;
     double inv_h;
     const double *qh;
+    const int32_t *bc;   // first cell index of each particle's stencil (overlap test)
     int32_t *count, *off, *cursor, *list, *key;
 };
 
@@ -983,31 +984,24 @@ __device__ __forceinline__ int axis_tiles(int f, int n, int ts, int out[3]) {
     return cnt;
 }
 
-__device__ __forceinline__ int particle_blocks(const BinArgs &b, int p, int out[27], int keys[27]) {
+__device__ __forceinline__ int particle_blocks(const BinArgs &b, int p, int out[27]) {
     int tx[3], ty[3], tz[3];
     const double *q = b.qh + 3 * p;
-    const int fz = (int)floor(q[2] * b.inv_h);
     const int cx = axis_tiles((int)floor(q[0] * b.inv_h), b.nx, TX, tx);
     const int cy = axis_tiles((int)floor(q[1] * b.inv_h), b.ny, TY, ty);
-    const int cz = axis_tiles(fz, b.nz, b.tz, tz);
+    const int cz = axis_tiles((int)floor(q[2] * b.inv_h), b.nz, b.tz, tz);
     int n = 0;
-    for (int k = 0; k < cz; ++k) {
-        const int z0 = tz[k] * b.tz;
-        const int key = (((fz - 1) - (z0 - 3)) % b.nz + b.nz) % b.nz;
+    for (int k = 0; k < cz; ++k)
         for (int j = 0; j < cy; ++j)
-            for (int i = 0; i < cx; ++i) {
-                keys[n] = key;
-                out[n++] = (tz[k] * b.gy + ty[j]) * b.gx + tx[i];
-            }
-    }
+            for (int i = 0; i < cx; ++i) out[n++] = (tz[k] * b.gy + ty[j]) * b.gx + tx[i];
     return n;
 }
 
 __global__ __launch_bounds__(256) void k_bin_count(const BinArgs b) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= b.np) return;
-    int bl[27], ky[27];
-    const int n = particle_blocks(b, p, bl, ky);
+    int bl[27];
+    const int n = particle_blocks(b, p, bl);
     for (int c = 0; c < n; ++c) atomicAdd(&b.count[bl[c]], 1);
 }
 
@@ -1041,60 +1035,107 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const BinArgs b) {
 __global__ __launch_bounds__(256) void k_bin_fill(const BinArgs b) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= b.np) return;
-    int bl[27], ky[27];
-    const int n = particle_blocks(b, p, bl, ky);
+    int bl[27];
+    const int n = particle_blocks(b, p, bl);
     for (int c = 0; c < n; ++c) {
         const int slot = atomicAdd(&b.cursor[bl[c]], 1);
         b.list[slot] = p;
-        b.key[slot] = ky[c];
     }
 }
 
-// One wave per block list: rank sort by (key, particle id) in LDS; lists
-// longer than the LDS buffer fall back to an insertion sort by lane 0.
+// One wave per block list.  The list (filled in arbitrary order) is sorted
+// by particle id, then coloured greedily in that order: a candidate takes
+// the smallest colour not used by an earlier candidate whose point box
+// overlaps its own (|d bc| <= 3 on every axis, periodic), so candidates of
+// one colour touch disjoint grid points.  The list is finally ordered by
+// (colour, id) and key[] holds the colour.  Lists longer than the LDS buffer
+// are sorted by lane 0 and get one colour per candidate.
 constexpr int SORT_CAP = 512;
 
+__device__ __forceinline__ bool boxes_overlap(const int a[3], const int b[3], const int n[3]) {
+    bool all = true;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        int d = a[ax] - b[ax];
+        if (d < 0) d = -d;
+        d = min(d, n[ax] - d);
+        all = all && d <= 3;
+    }
+    return all;
+}
+
 __global__ __launch_bounds__(64) void k_bin_sort(const BinArgs b) {
-    __shared__ int32_t sk[SORT_CAP], sp[SORT_CAP];
+    __shared__ int32_t sp[SORT_CAP], sq[SORT_CAP], sc[SORT_CAP], sb[SORT_CAP][3];
     const int blk = blockIdx.x;
     const int lane = threadIdx.x;
     const int s0 = b.off[blk], n = b.off[blk + 1] - s0;
-    if (n <= 1) return;
-    if (n <= SORT_CAP) {
-        for (int i = lane; i < n; i += 64) {
-            sk[i] = b.key[s0 + i];
-            sp[i] = b.list[s0 + i];
+    if (n == 0) return;
+    if (n > SORT_CAP) {
+        if (lane != 0) return;
+        for (int m = s0 + 1; m < s0 + n; ++m) {
+            const int v = b.list[m];
+            int j = m - 1;
+            while (j >= s0 && b.list[j] > v) {
+                b.list[j + 1] = b.list[j];
+                --j;
+            }
+            b.list[j + 1] = v;
         }
-        __syncthreads();
-        for (int i = lane; i < n; i += 64) {
-            const int ki = sk[i], pi = sp[i];
-            int rank = 0;
-            for (int j = 0; j < n; ++j) rank += (sk[j] < ki) || (sk[j] == ki && sp[j] < pi);
-            b.list[s0 + rank] = pi;
-            b.key[s0 + rank] = ki;
-        }
+        for (int i = 0; i < n; ++i) b.key[s0 + i] = i;
         return;
     }
-    if (lane != 0) return;
-    for (int m = s0 + 1; m < s0 + n; ++m) {
-        const int v = b.list[m], kv = b.key[m];
-        int j = m - 1;
-        while (j >= s0 && (b.key[j] > kv || (b.key[j] == kv && b.list[j] > v))) {
-            b.list[j + 1] = b.list[j];
-            b.key[j + 1] = b.key[j];
-            --j;
+    const int nn[3] = {b.nx, b.ny, b.nz};
+    for (int i = lane; i < n; i += 64) sq[i] = b.list[s0 + i];
+    __syncthreads();
+    // rank sort by particle id (ids in one list are distinct)
+    for (int i = lane; i < n; i += 64) {
+        const int pi = sq[i];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) rank += sq[j] < pi;
+        sp[rank] = pi;
+    }
+    __syncthreads();
+    for (int i = lane; i < n; i += 64) {
+        const int pi = sp[i];
+        sb[i][0] = b.bc[3 * pi];
+        sb[i][1] = b.bc[3 * pi + 1];
+        sb[i][2] = b.bc[3 * pi + 2];
+    }
+    __syncthreads();
+    // greedy colouring in id order (the wave takes candidates one at a time)
+    for (int i = 0; i < n; ++i) {
+        unsigned long long used = 0;
+        int far = 0;   // colours >= 64 in use by an overlapping candidate
+        for (int j = lane; j < i; j += 64) {
+            if (boxes_overlap(sb[i], sb[j], nn)) {
+                if (sc[j] < 64) used |= 1ull << sc[j];
+                else far = max(far, sc[j] + 1);
+            }
         }
-        b.list[j + 1] = v;
-        b.key[j + 1] = kv;
+        for (int o = 32; o >= 1; o >>= 1) {
+            used |= __shfl_xor(used, o, 64);
+            far = max(far, __shfl_xor(far, o, 64));
+        }
+        const int c = ~used ? __builtin_ctzll(~used) : max(64, far);
+        if (lane == 0) sc[i] = c;
+        __syncthreads();
+    }
+    // order by (colour, id)
+    for (int i = lane; i < n; i += 64) {
+        const int ci = sc[i];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) rank += sc[j] < ci || (sc[j] == ci && j < i);
+        b.list[s0 + rank] = sp[i];
+        b.key[s0 + rank] = ci;
     }
 }
 
 // Sparse owner-computes updates of the grid near particles, one stage block
-// per workgroup.  Each block stages its candidate particles in LDS and
-// applies their contributions to its own grid points only, in list order:
-// candidates whose point boxes do not overlap run together, others one
-// after the other, so every point receives its sums in the same order on
-// every run (no float atomics).  Modes:
+// per workgroup.  The block's candidates arrive ordered by (colour, id) from
+// k_bin_sort; candidates of one colour touch disjoint points, so each colour
+// is one parallel round over (candidate, point) items and every point
+// receives its sums in the same order on every run (no float atomics).
+// Modes:
 //   SP_SPREAD : field += f_p w_p / h^3 (caller spreading, one location kind)
 //   SP_NOSLIP : g^a += rho_face V w_a (u^{n+1} - V~)^a / h^3 (substep 6)
 //   SP_STAGE  : g^a += b [-(dt/h) (P(i+a) - P(i)) + dt F^a w_a / h^3] with
@@ -1106,7 +1147,7 @@ template <typename T>
 struct SparseArgs {
     int nx, ny, nz, tz;
     double inv_h3, rho0, b, dt_h, dt;
-    const int32_t *blk_off, *blk_list, *bc, *bf;
+    const int32_t *blk_off, *blk_list, *blk_color, *bc, *bf;
     const double *wc, *wf;
     const double *val;   // SPREAD: f[p]; NOSLIP: du[p][3]; STAGE: F[p][3]
     const double *omega; // STAGE only
@@ -1115,13 +1156,13 @@ struct SparseArgs {
     const T *drho;       // NOSLIP only
 };
 
-constexpr int SP_CAP = 128;  // candidates staged in LDS at a time
+constexpr int SP_CAP = 128;   // candidates staged in LDS at a time
+constexpr int SP_BATCH = 4;   // items per thread whose loads are issued together
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(STAGE_THREADS) void k_sparse(const SparseArgs<T> a) {
-    __shared__ int32_t s_bc[SP_CAP][3], s_bf[SP_CAP][3];
+    __shared__ int32_t s_bc[SP_CAP][3], s_bf[SP_CAP][3], s_col[SP_CAP];
     __shared__ double s_wc[SP_CAP][9], s_wf[SP_CAP][9], s_v[SP_CAP][4];
-    __shared__ int s_clash;
     const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     const int cb = a.blk_off[blk], ce = a.blk_off[blk + 1];
     if (cb == ce) return;
@@ -1134,13 +1175,13 @@ __global__ __launch_bounds__(STAGE_THREADS) void k_sparse(const SparseArgs<T> a)
     constexpr int ncomp = MODE == SP_SPREAD ? 1 : 3;
     constexpr int per_comp = MODE == SP_STAGE ? 36 : 27;
     constexpr int per = ncomp * per_comp;
-    constexpr int group = STAGE_THREADS / per;
 
     for (int c0 = cb; c0 < ce; c0 += SP_CAP) {
         const int nc = min(SP_CAP, ce - c0);
         __syncthreads();
         for (int i = tid; i < nc; i += STAGE_THREADS) {
             const int pid = a.blk_list[c0 + i];
+            s_col[i] = a.blk_color[c0 + i];
             for (int d = 0; d < 3; ++d) {
                 s_bc[i][d] = a.bc[3 * pid + d];
                 s_bf[i][d] = a.bf[3 * pid + d];
@@ -1157,32 +1198,27 @@ __global__ __launch_bounds__(STAGE_THREADS) void k_sparse(const SparseArgs<T> a)
             }
         }
         __syncthreads();
-        for (int g0 = 0; g0 < nc; g0 += group) {
-            const int g1 = min(g0 + group, nc);
-            // overlap test of the group's point boxes [bc-1, bc+2] per axis
-            if (tid == 0) {
-                int clash = 0;
-                for (int i = g0; i < g1 && !clash; ++i)
-                    for (int j = i + 1; j < g1 && !clash; ++j) {
-                        bool all = true;
-                        for (int ax = 0; ax < 3; ++ax) {
-                            int d = s_bc[i][ax] - s_bc[j][ax];
-                            if (d < 0) d = -d;
-                            d = min(d, n[ax] - d);
-                            all = all && d <= 3;
-                        }
-                        clash = all;
-                    }
-                s_clash = clash;
-            }
-            __syncthreads();
-            const bool clash = s_clash != 0;
-            const int rounds = clash ? g1 - g0 : 1;
-            for (int r = 0; r < rounds; ++r) {
-                const int ci = clash ? g0 + r : g0 + tid / per;
-                const bool active = clash ? tid < per : (tid < (g1 - g0) * per);
-                if (active) {
-                    const int item = tid % per;
+        for (int r0 = 0; r0 < nc;) {
+            // one colour: candidates [r0, r1)
+            const int col = s_col[r0];
+            int r1 = r0 + 1;
+            while (r1 < nc && s_col[r1] == col) ++r1;
+            const int items = (r1 - r0) * per;
+            for (int base = 0; base < items; base += SP_BATCH * STAGE_THREADS) {
+                size_t gi[SP_BATCH];
+                double add[SP_BATCH];
+                int cmp[SP_BATCH];
+                bool ok[SP_BATCH];
+#pragma unroll
+                for (int bi = 0; bi < SP_BATCH; ++bi) {
+                    const int it = base + bi * STAGE_THREADS + tid;
+                    ok[bi] = false;
+                    gi[bi] = 0;
+                    add[bi] = 0.0;
+                    cmp[bi] = 0;
+                    if (it >= items) continue;
+                    const int ci = r0 + it / per;
+                    const int item = it % per;
                     const int comp = item / per_comp, pt = item % per_comp;
                     const int kind = MODE == SP_SPREAD ? a.kind : 1 + comp;
                     const int fa = kind - 1;  // face axis, -1 for cells
@@ -1211,43 +1247,53 @@ __global__ __launch_bounds__(STAGE_THREADS) void k_sparse(const SparseArgs<T> a)
                         pos[ax] = wrap(start + d[ax], n[ax]);
                         in = in && pos[ax] >= lo[ax] && pos[ax] < lo[ax] + wd[ax];
                     }
-                    if (in) {
-                        const size_t g = ((size_t)pos[2] * ny + pos[1]) * nx + pos[0];
-                        // weight of the cell (face == -1) or face stencil at pos
-                        auto weight = [&](const int p[3], int face) {
-                            double w = 1.0;
-                            for (int ax = 0; ax < 3; ++ax) {
-                                const bool f = ax == face;
-                                int o = p[ax] - (f ? s_bf[ci][ax] : s_bc[ci][ax]);
-                                if (o < 0) o += n[ax];
-                                if (o >= 3) return 0.0;
-                                w *= f ? s_wf[ci][3 * ax + o] : s_wc[ci][3 * ax + o];
-                            }
-                            return w;
-                        };
-                        double add;
-                        if (MODE == SP_SPREAD) {
-                            add = s_v[ci][0] * weight(pos, fa) * a.inv_h3;
-                        } else if (MODE == SP_NOSLIP) {
-                            int nb[3] = {pos[0], pos[1], pos[2]};
-                            nb[fa] = nb[fa] + 1 == n[fa] ? 0 : nb[fa] + 1;
-                            const size_t j = ((size_t)nb[2] * ny + nb[1]) * nx + nb[0];
-                            const double rf = a.rho0 + 0.5 * ((double)a.drho[g] + (double)a.drho[j]);
-                            add = rf * s_v[ci][comp] * weight(pos, fa) * a.inv_h3;
-                        } else {
-                            int nb[3] = {pos[0], pos[1], pos[2]};
-                            nb[fa] = nb[fa] + 1 == n[fa] ? 0 : nb[fa] + 1;
-                            const double om = s_v[ci][3];
-                            const double dP = om * (weight(nb, -1) - weight(pos, -1)) * a.inv_h3;
-                            const double fw = s_v[ci][comp] * weight(pos, fa) * a.inv_h3;
-                            add = a.b * (-a.dt_h * dP + a.dt * fw);
+                    if (!in) continue;
+                    const size_t g = ((size_t)pos[2] * ny + pos[1]) * nx + pos[0];
+                    // weight of the cell (face == -1) or face stencil at p
+                    auto weight = [&](const int p[3], int face) {
+                        double w = 1.0;
+                        for (int ax = 0; ax < 3; ++ax) {
+                            const bool f = ax == face;
+                            int o = p[ax] - (f ? s_bf[ci][ax] : s_bc[ci][ax]);
+                            if (o < 0) o += n[ax];
+                            if (o >= 3) return 0.0;
+                            w *= f ? s_wf[ci][3 * ax + o] : s_wc[ci][3 * ax + o];
                         }
-                        T *fld = a.fields[comp];
-                        fld[g] = (T)((double)fld[g] + add);
+                        return w;
+                    };
+                    double v;
+                    if (MODE == SP_SPREAD) {
+                        v = s_v[ci][0] * weight(pos, fa) * a.inv_h3;
+                    } else if (MODE == SP_NOSLIP) {
+                        int nb[3] = {pos[0], pos[1], pos[2]};
+                        nb[fa] = nb[fa] + 1 == n[fa] ? 0 : nb[fa] + 1;
+                        const size_t j = ((size_t)nb[2] * ny + nb[1]) * nx + nb[0];
+                        const double rf = a.rho0 + 0.5 * ((double)a.drho[g] + (double)a.drho[j]);
+                        v = rf * s_v[ci][comp] * weight(pos, fa) * a.inv_h3;
+                    } else {
+                        int nb[3] = {pos[0], pos[1], pos[2]};
+                        nb[fa] = nb[fa] + 1 == n[fa] ? 0 : nb[fa] + 1;
+                        const double om = s_v[ci][3];
+                        const double dP = om * (weight(nb, -1) - weight(pos, -1)) * a.inv_h3;
+                        const double fw = s_v[ci][comp] * weight(pos, fa) * a.inv_h3;
+                        v = a.b * (-a.dt_h * dP + a.dt * fw);
                     }
+                    ok[bi] = true;
+                    gi[bi] = g;
+                    add[bi] = v;
+                    cmp[bi] = comp;
                 }
-                __syncthreads();
+                // the batch's points are distinct: issue every load, then every store
+                T old[SP_BATCH];
+#pragma unroll
+                for (int bi = 0; bi < SP_BATCH; ++bi)
+                    old[bi] = ok[bi] ? a.fields[cmp[bi]][gi[bi]] : (T)0;
+#pragma unroll
+                for (int bi = 0; bi < SP_BATCH; ++bi)
+                    if (ok[bi]) a.fields[cmp[bi]][gi[bi]] = (T)((double)old[bi] + add[bi]);
             }
+            __syncthreads();
+            r0 = r1;
         }
     }
 }
@@ -1318,6 +1364,7 @@ BinArgs bin_args(ic_ctx *c, int np, const double *qh) {
     b.cursor = c->ws.blk_cursor;
     b.list = c->ws.blk_list;
     b.key = c->ws.blk_key;
+    b.bc = c->ws.pk.bc;
     return b;
 }
 
@@ -1342,7 +1389,7 @@ SparseArgs<T> sparse_args(ic_ctx *c) {
     sa.rho0 = p.rho0;
     sa.dt_h = p.dt / p.h;
     sa.dt = p.dt;
-    sa.blk_off = w.blk_off; sa.blk_list = w.blk_list;
+    sa.blk_off = w.blk_off; sa.blk_list = w.blk_list; sa.blk_color = w.blk_key;
     sa.bc = w.pk.bc; sa.bf = w.pk.bf; sa.wc = w.pk.wc; sa.wf = w.pk.wf;
     return sa;
 }

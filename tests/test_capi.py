@@ -37,6 +37,7 @@ def _params(**kw):
 @pytest.mark.parametrize("kw,code", [
     (dict(nx=3), -1), (dict(h=0.0), -1), (dict(eta=-1.0), -1), (dict(prec=7), -1),
     (dict(kT=float("nan")), -1), (dict(max_particles=-1), -1),
+    (dict(nx=1024, ny=1024, nz=1024, prec=1), -1), (dict(nx=1024, ny=1024, nz=512, prec=2), -1),
     (dict(dt=0.6), -2), (dict(eta=3.0, dt=0.1), -2),
 ])
 def test_create_rejects_bad_params(kw, code):
