@@ -9,9 +9,9 @@ Grid arrays have shape (nz, ny, nx) (x fastest in memory); particle arrays are
 (N, 3) with columns x, y, z.
 
 Workloads (all synthetic: the paper measures nothing on external data):
-  * "standing-wave-32"  : 32^3, kT = 0, one tethered particle at x = 4 in a
-    modal standing wave of density amplitude 1e-3 (the deterministic Gor'kov
-    case; FP64).
+  * "standing-wave-32"  : 32^3, kT = 0, a symmetric pair of tethered
+    particles in a modal standing wave of density amplitude 1e-3 (the
+    deterministic radiation-force case; FP64).
   * "thermal-128"       : 128^3, kT = 1e-3, 1000 particles, wave 1e-2.
   * "paper-scale-256"   : 256^3, kT = 1e-3, 10^4 particles, half of each
     acoustic-contrast sign, wave 1e-2 (the benchmark workload).
@@ -227,17 +227,28 @@ def split_contrast_particles(fl: Fluid, n, seed, ks, threshold=0.05):
 # Named workloads
 # ----------------------------------------------------------------------------
 
-def standing_wave_32(ks=10.0, x=4.0):
-    """32^3, kT = 0, one particle with m_p = 2 rho0 V and kappa_p = kappa_f/2 at
-    (x, 16, 16), tethered there; cosine drive along x with density amplitude
-    1e-3, whole-step period; fluid starts on the driven standing wave."""
+def soft_tether(fl: Fluid, omega, mp_min):
+    """Spring constant whose tether frequency is a sixth of the drive
+    frequency for the lightest particle: the particles then oscillate with
+    the wave (as the radiation force assumes) while the spring holds their
+    mean position."""
+    return mp_min * (omega / 6.0) ** 2
+
+
+def standing_wave_32(x=4.0):
+    """32^3, kT = 0: a symmetric pair of particles with m_p = 2 rho0 V and
+    kappa_p = kappa_f/2, tethered at x0 + x and x0 - x from the pressure
+    antinode x0 = 0 (y, z = L/2 and 0, so the springs' momenta cancel);
+    cosine drive along x with density amplitude 1e-3, whole-step period;
+    fluid starts on the driven standing wave."""
     fl = Fluid(32, 32, 32, kT=0.0, seed=1)
     V = 8.0
     mode, nT = modal_drive(fl, 1e-3)
     drho, g = standing_wave_fields(fl, 1e-3, omega=mode.omega)
-    q = np.array([[x, 16.0, 16.0]])
-    p = Particles(q=q, me=np.array([2.0 * V - V]), kappa_ratio=np.array([0.5]),
-                  ks=np.array([ks]), qeq=q.copy())
+    q = np.array([[x, 16.0, 16.0], [32.0 - x, 0.0, 0.0]])
+    ks = soft_tether(fl, mode.omega, 2.0 * V)
+    p = Particles(q=q, me=np.full(2, 2.0 * V - V), kappa_ratio=np.full(2, 0.5),
+                  ks=np.full(2, ks), qeq=q.copy())
     return Workload("standing-wave-32", fl, p, [mode], drho, g, nT)
 
 
@@ -245,7 +256,7 @@ def thermal_128(n=1000, seed=2):
     fl = Fluid(128, 128, 128, kT=1e-3, seed=seed)
     mode, nT = modal_drive(fl, 1e-2)
     drho, g = standing_wave_fields(fl, 1e-2, omega=mode.omega)
-    p = uniform_particles(fl, n, seed, ks=10.0)
+    p = uniform_particles(fl, n, seed, ks=soft_tether(fl, mode.omega, 4.0))
     return Workload("thermal-128", fl, p, [mode], drho, g, nT)
 
 
@@ -253,7 +264,7 @@ def paper_scale_256(n=10000, seed=3):
     fl = Fluid(256, 256, 256, kT=1e-3, seed=seed)
     mode, nT = modal_drive(fl, 1e-2)
     drho, g = standing_wave_fields(fl, 1e-2, omega=mode.omega)
-    p = split_contrast_particles(fl, n, seed, ks=10.0)
+    p = split_contrast_particles(fl, n, seed, ks=soft_tether(fl, mode.omega, 4.0))
     return Workload("paper-scale-256", fl, p, [mode], drho, g, nT)
 
 
