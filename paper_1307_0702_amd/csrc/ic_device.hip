@@ -93,14 +93,72 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 
 template <typename T>
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, T &z0, T &z1);
+// FP64 Box-Muller on the 24-bit grid of the uniforms: u = m 2^-24 with m odd.
+// ln u = (e - 24) ln 2 + ln f for m = f 2^e, f in [1/sqrt2, sqrt2), with
+// ln f = 2 atanh(s), s = (f - 1)/(f + 1), |s| < 0.172, from its power series
+// (terms to s^21, truncation below 1e-17 relative).
+__device__ __forceinline__ double ln_grid24(uint32_t m) {
+    int e = 31 - __builtin_clz(m);
+    double f = __builtin_ldexp((double)m, -e);     // [1, 2)
+    if (f > 1.4142135623730951) {
+        f *= 0.5;
+        e += 1;
+    }
+    const double s = (f - 1.0) / (f + 1.0), z = s * s;
+    double p = 1.0 / 21;
+    p = fma(p, z, 1.0 / 19);
+    p = fma(p, z, 1.0 / 17);
+    p = fma(p, z, 1.0 / 15);
+    p = fma(p, z, 1.0 / 13);
+    p = fma(p, z, 1.0 / 11);
+    p = fma(p, z, 1.0 / 9);
+    p = fma(p, z, 1.0 / 7);
+    p = fma(p, z, 1.0 / 5);
+    p = fma(p, z, 1.0 / 3);
+    p = fma(p, z, 1.0);
+    return (double)(e - 24) * 0.6931471805599453 + 2.0 * s * p;
+}
+
+// cos and sin of the angle 2 pi n 2^-24: exact reduction to the nearest
+// quarter turn in integers, then the Taylor series of sin (to th^15) and cos
+// (to th^16) on |th| <= pi/4 (truncation below 7e-17).
+__device__ __forceinline__ void sincos_grid24(uint32_t n, double &sn, double &cs) {
+    const uint32_t q = (n + (1u << 21)) >> 22;      // nearest quarter turn, 0..4
+    const int j = (int)n - (int)(q << 22);           // [-2^21, 2^21]
+    const double th = (double)j * (6.283185307179586 * 0x1p-24);
+    const double z = th * th;
+    double ps = -1.0 / 1307674368000.0;
+    ps = fma(ps, z, 1.0 / 6227020800.0);
+    ps = fma(ps, z, -1.0 / 39916800.0);
+    ps = fma(ps, z, 1.0 / 362880.0);
+    ps = fma(ps, z, -1.0 / 5040.0);
+    ps = fma(ps, z, 1.0 / 120.0);
+    ps = fma(ps, z, -1.0 / 6.0);
+    const double s0 = fma(th * z, ps, th);
+    double pc = 1.0 / 20922789888000.0;
+    pc = fma(pc, z, -1.0 / 87178291200.0);
+    pc = fma(pc, z, 1.0 / 479001600.0);
+    pc = fma(pc, z, -1.0 / 3628800.0);
+    pc = fma(pc, z, 1.0 / 40320.0);
+    pc = fma(pc, z, -1.0 / 720.0);
+    pc = fma(pc, z, 1.0 / 24.0);
+    pc = fma(pc, z, -0.5);
+    const double c0 = fma(z, pc, 1.0);
+    switch (q & 3u) {
+        case 0: cs = c0; sn = s0; break;
+        case 1: cs = -s0; sn = c0; break;
+        case 2: cs = -c0; sn = -s0; break;
+        default: cs = s0; sn = -c0; break;
+    }
+}
+
 template <>
 __device__ __forceinline__ void box_muller<double>(uint32_t a, uint32_t b, double &z0,
                                                    double &z1) {
-    // uniforms ((x >> 9) + 1/2) 2^-23, exact in FP32 and FP64
-    const double u1 = ((double)(a >> 9) + 0.5) * 0x1p-23, u2 = ((double)(b >> 9) + 0.5) * 0x1p-23;
-    const double r = sqrt(-2.0 * log(u1));
+    // uniforms ((x >> 9) + 1/2) 2^-23 = (2 (x >> 9) + 1) 2^-24
+    const double r = sqrt(-2.0 * ln_grid24(2u * (a >> 9) + 1u));
     double s, c;
-    sincospi(2.0 * u2, &s, &c);
+    sincos_grid24(2u * (b >> 9) + 1u, s, c);
     z0 = r * c;
     z1 = r * s;
 }
@@ -225,14 +283,22 @@ __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, uint3
 // Imposed pressure at cell (x, y, z).  The particle pressure S Omega and the
 // spread force S F are added after the sweep (k_sparse, stage mode): both
 // enter the stage output linearly.
+// Split as p_ext(x, y) + p_ext(z): the x and y parts are fixed for a column,
+// the z part is uniform over a plane.
 template <typename T>
-__device__ __forceinline__ T ext_pressure(const StageArgs<T> &a, int x, int y, int z) {
+__device__ __forceinline__ T ext_pressure_xy(const StageArgs<T> &a, int x, int y) {
     T s = 0;
     for (int m = 0; m < a.nmodes; ++m) {
         const int ax = a.maxis[m];
-        const int coord = ax == 0 ? x : (ax == 1 ? y : z);
-        s += a.mamp[m] * (T)a.prof[m * a.pstride + coord];
+        if (ax != 2) s += a.mamp[m] * (T)a.prof[m * a.pstride + (ax == 0 ? x : y)];
     }
+    return s;
+}
+template <typename T>
+__device__ __forceinline__ T ext_pressure_z(const StageArgs<T> &a, int z) {
+    T s = 0;
+    for (int m = 0; m < a.nmodes; ++m)
+        if (a.maxis[m] == 2) s += a.mamp[m] * (T)a.prof[m * a.pstride + z];
     return s;
 }
 
@@ -248,7 +314,7 @@ __device__ __forceinline__ T ext_pressure(const StageArgs<T> &a, int x, int y, i
 // the fluxes the tile's own faces need there) and wave 4 the rest of the
 // density ring.  Register sets for planes k+1 and k+2 alternate, so every
 // load is issued one iteration before its use.
-template <typename T, int STAGE, bool NOISE>
+template <typename T, int STAGE, bool NOISE, bool FULL>
 __global__ __launch_bounds__(STAGE_THREADS)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void stage_kernel(const StageArgs<T> a) {
     __shared__ T s_G[3][PS], s_V[3][PS], s_P[2][PS], s_F[6][PS];
@@ -268,7 +334,9 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void stage_kernel(c
         bz = t / (a.gx * a.gy);
     }
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * tz;   // z0 is even (tz is)
-    const int W = min(TX, nx - x0), Wy = min(TY, ny - y0), z1 = min(z0 + tz, nz);
+    // FULL: every tile is whole (nx, ny multiples of TX, TY)
+    const int W = FULL ? TX : min(TX, nx - x0), Wy = FULL ? TY : min(TY, ny - y0);
+    const int z1 = min(z0 + tz, nz);
     const T rho0 = a.rho0, half = (T)0.5, quarter = (T)0.25;
 
     __amdgpu_buffer_rsrc_t rin[4], run[4], rnn[3], rout[4];
@@ -286,7 +354,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void stage_kernel(c
 
     // own column
     const int lx = tid % TX, ly = tid / TX;
-    const bool own = lx < W && ly < Wy;
+    const bool own = FULL || (lx < W && ly < Wy);
     const int lo = lidx(lx, ly);
     const int xo = x0 + lx, yo = y0 + ly;
     const uint32_t vo = own ? (uint32_t)(yo * nx + xo) * (uint32_t)sizeof(T) : 0u;
@@ -320,6 +388,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void stage_kernel(c
     }
     const int l1 = lidx(r1x, r1y), l2 = lidx(r2x, r2y);
     const int g1x = wrap(x0 + r1x, nx), g1y = wrap(y0 + r1y, ny);
+    const T pex_own = own ? ext_pressure_xy(a, xo, yo) : (T)0;
+    const T pex_r1 = r1 ? ext_pressure_xy(a, g1x, g1y) : (T)0;
     const uint32_t v1 = r1 ? (uint32_t)(g1y * nx + g1x) * (uint32_t)sizeof(T) : 0u;
     const uint32_t v2 =
         r2 ? (uint32_t)(wrap(y0 + r2y, ny) * nx + wrap(x0 + r2x, nx)) * (uint32_t)sizeof(T) : 0u;
@@ -414,6 +484,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void stage_kernel(c
         const T *gx = s_G[0], *gy = s_G[1], *gz = s_G[2];
         const T *vx = s_V[0], *vy = s_V[1], *vz = s_V[2];
         const int zk = k;                   // k in [z0-1, z1)
+        const T pez = PREP ? (T)0 : ext_pressure_z(a, wrap(zk, nz));
         // ---- phase B: velocities of plane k+1, fluxes of plane k
         T vn[3] = {0, 0, 0}, vn1[3] = {0, 0, 0};
         T un[4] = {0, 0, 0, 0}, nn[3] = {0, 0, 0}, mflux = 0, Pxz = 0, Pyz = 0;
@@ -436,7 +507,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void stage_kernel(c
             Pxz = quarter * (gx[l] + S.g[0]) * (vz[l] + vz[l + 1]) - viz_x;
             Pyz = quarter * (gy[l] + S.g[1]) * (vz[l] + vz[l + PX]) - viz_y;
             if (!PREP) {
-                const T pi = a.cf2 * Pk[l] + ext_pressure(a, xo, yo, wrap(zk, nz));
+                const T pi = a.cf2 * Pk[l] + (pex_own + pez);
                 const T dvx = vx[l] - vx[l - 1], dvy = vy[l] - vy[l - PX], dvz = vz[l] - vzm;
                 const T ldiv = a.lam * ((dvx + dvy + dvz) * a.inv_h);
                 const T Pzz = pi + quarter * (gz[l] + gzm) * (vz[l] + vzm) -
@@ -464,13 +535,13 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void stage_kernel(c
             vel(S.g1, P1[l], P1[l + 1], P1[l + PX], S.rn1, vn1);
             if (!PREP && r1f) {
                 if (wave == 0) {            // +x column: centre flux xx
-                    const T pi = a.cf2 * Pk[l] + ext_pressure(a, g1x, g1y, wrap(zk, nz));
+                    const T pi = a.cf2 * Pk[l] + (pex_r1 + pez);
                     const T dvx = vx[l] - vx[l - 1];
                     const T div = (dvx + (vy[l] - vy[l - PX]) + (vz[l] - vzm1)) * a.inv_h;
                     s_F[0][l] = pi + quarter * (gx[l] + gx[l - 1]) * (vx[l] + vx[l - 1]) -
                                 (2 * a.eta * dvx * a.inv_h + a.lam * div);
                 } else if (wave == 2) {     // +y row: centre flux yy
-                    const T pi = a.cf2 * Pk[l] + ext_pressure(a, g1x, g1y, wrap(zk, nz));
+                    const T pi = a.cf2 * Pk[l] + (pex_r1 + pez);
                     const T dvy = vy[l] - vy[l - PX];
                     const T div = ((vx[l] - vx[l - 1]) + dvy + (vz[l] - vzm1)) * a.inv_h;
                     s_F[1][l] = pi + quarter * (gy[l] + gy[l - PX]) * (vy[l] + vy[l - PX]) -
@@ -550,7 +621,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void stage_kernel(c
         const int l = lo;
         const T *Pz = s_P[z1 & 1];
         const T *gz = s_G[2], *vx = s_V[0], *vy = s_V[1], *vz = s_V[2];
-        const T pi = a.cf2 * Pz[l] + ext_pressure(a, xo, yo, wrap(z1, nz));
+        const T pi = a.cf2 * Pz[l] + (pex_own + ext_pressure_z(a, wrap(z1, nz)));
         const T dvz = vz[l] - vzm;
         const T div = ((vx[l] - vx[l - 1]) + (vy[l] - vy[l - PX]) + dvz) * a.inv_h;
         const T Pzz = pi + quarter * (gz[l] + gzm) * (vz[l] + vzm) -
@@ -576,12 +647,25 @@ struct NoiseArgs {
     NoiseKey nk;
 };
 
+// Tile of the noise kernel: 32 x NTY<T> columns (32 in FP32, 16 in FP64,
+// whose registers and LDS are twice as wide).  Waves 0-3 also take one side
+// each of the ring of cells whose stresses the tile's faces need (+x column:
+// xx, +y row: yy, -x column: xy and xz, -y row: xy and yz), so each SIMD
+// carries one ring wave.
+constexpr int NTX = 32, NPX = NTX + 2;
 template <typename T>
-__global__ __launch_bounds__(STAGE_THREADS) void noise_kernel(const NoiseArgs<T> a) {
-    __shared__ T s_S[2][5][PS];  // [W_A, W_B][xx, yy, xy, xz, yz] at the current plane
+constexpr int NTY = sizeof(T) == 4 ? 32 : 16;
+template <typename T>
+constexpr int NOISE_THREADS = NTX * NTY<T>;
+
+__device__ __forceinline__ int nidx(int lx, int ly) { return (ly + 1) * NPX + (lx + 1); }
+
+template <typename T>
+__global__ __launch_bounds__(NOISE_THREADS<T>) void noise_kernel(const NoiseArgs<T> a) {
+    __shared__ T s_S[2][5][NPX * (NTY<T> + 2)];  // [W_A, W_B][xx, yy, xy, xz, yz], current plane
     const int nx = a.nx, ny = a.ny, nz = a.nz, tz = a.tz;
     const int plane = nx * ny;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     int bx, by, bz;
     {
         const int nblk = a.gx * a.gy * a.gz, b = blockIdx.x;
@@ -591,26 +675,20 @@ __global__ __launch_bounds__(STAGE_THREADS) void noise_kernel(const NoiseArgs<T>
         by = (t / a.gx) % a.gy;
         bz = t / (a.gx * a.gy);
     }
-    const int x0 = bx * TX, y0 = by * TY, z0 = bz * tz;
-    const int W = min(TX, nx - x0), Wy = min(TY, ny - y0), z1 = min(z0 + tz, nz);
-    const int lx = tid % TX, ly = tid / TX;
+    const int x0 = bx * NTX, y0 = by * NTY<T>, z0 = bz * tz;
+    const int W = min(NTX, nx - x0), Wy = min(NTY<T>, ny - y0), z1 = min(z0 + tz, nz);
+    const int lx = tid % NTX, ly = tid / NTX;
     const bool own = lx < W && ly < Wy;
-    const int li = lidx(lx, ly);
+    const int li = nidx(lx, ly);
     const int own_xy = own ? (y0 + ly) * nx + x0 + lx : 0;
-    int h_type = -1, h_x = 0, h_y = 0;
-    {
-        const int i = tid < 64 ? tid : tid - 64;
-        if (tid < 128 && i < Wy + W) {
-            if (tid < 64) {
-                if (i < Wy) { h_type = 0; h_x = W; h_y = i; }
-                else { h_type = 1; h_x = i - Wy; h_y = Wy; }
-            } else {
-                if (i < Wy) { h_type = 2; h_x = -1; h_y = i; }
-                else { h_type = 3; h_x = i - Wy; h_y = -1; }
-            }
-        }
-    }
-    const int h_l = lidx(h_x, h_y);
+    // ring cell of waves 0-3
+    int h_x = 0, h_y = 0;
+    bool ring = false;
+    if (wave == 0 && lane < Wy) { ring = true; h_x = W; h_y = lane; }
+    else if (wave == 1 && lane < W) { ring = true; h_x = lane; h_y = Wy; }
+    else if (wave == 2 && lane < Wy) { ring = true; h_x = -1; h_y = lane; }
+    else if (wave == 3 && lane < W) { ring = true; h_x = lane; h_y = -1; }
+    const int h_l = nidx(h_x, h_y);
     const int h_xy = wrap(y0 + h_y, ny) * nx + wrap(x0 + h_x, nx);
 
     // own stresses: planes k and k+1 (all components), plane k-1 (xz, yz)
@@ -638,21 +716,21 @@ __global__ __launch_bounds__(STAGE_THREADS) void noise_kernel(const NoiseArgs<T>
             s_S[1][0][l] = SBc[0]; s_S[1][1][l] = SBc[1]; s_S[1][2][l] = SBc[3];
             s_S[1][3][l] = SBc[4]; s_S[1][4][l] = SBc[5];
         }
-        if (h_type >= 0) {
+        if (ring) {
             T A[6] = {0, 0, 0, 0, 0, 0}, B[6] = {0, 0, 0, 0, 0, 0}, SA[6], SB[6];
             const uint32_t hc = (uint32_t)(k * plane + h_xy);
-            if (h_type <= 1)
+            if (wave < 2)
                 cell_normals<T, SEL_DIAG>(hc, a.nk, A, B);
             else
                 cell_normals<T, SEL_EDGE>(hc, a.nk, A, B);
             ll_stress(A, a.sd, a.st, a.so, SA);
             ll_stress(B, a.sd, a.st, a.so, SB);
             const int l = h_l;
-            if (h_type == 0) {
+            if (wave == 0) {
                 s_S[0][0][l] = SA[0]; s_S[1][0][l] = SB[0];
-            } else if (h_type == 1) {
+            } else if (wave == 1) {
                 s_S[0][1][l] = SA[1]; s_S[1][1][l] = SB[1];
-            } else if (h_type == 2) {
+            } else if (wave == 2) {
                 s_S[0][2][l] = SA[3]; s_S[1][2][l] = SB[3];
                 s_S[0][3][l] = SA[4]; s_S[1][3][l] = SB[4];
             } else {
@@ -669,9 +747,9 @@ __global__ __launch_bounds__(STAGE_THREADS) void noise_kernel(const NoiseArgs<T>
                 const T *Sc = w == 0 ? SAc : SBc, *Sp = w == 0 ? SAp : SBp, *Sn = w == 0 ? SAn : SBn;
                 const T *xx = s_S[w][0], *yy = s_S[w][1], *xy = s_S[w][2], *xz = s_S[w][3],
                         *yz = s_S[w][4];
-                N[w][0] = a.dt_h * ((xx[l + 1] - xx[l]) + (xy[l] - xy[l - PX]) + (Sc[4] - Sp[4]));
-                N[w][1] = a.dt_h * ((yy[l + PX] - yy[l]) + (xy[l] - xy[l - 1]) + (Sc[5] - Sp[5]));
-                N[w][2] = a.dt_h * ((Sn[2] - Sc[2]) + (xz[l] - xz[l - 1]) + (yz[l] - yz[l - PX]));
+                N[w][0] = a.dt_h * ((xx[l + 1] - xx[l]) + (xy[l] - xy[l - NPX]) + (Sc[4] - Sp[4]));
+                N[w][1] = a.dt_h * ((yy[l + NPX] - yy[l]) + (xy[l] - xy[l - 1]) + (Sc[5] - Sp[5]));
+                N[w][2] = a.dt_h * ((Sn[2] - Sc[2]) + (xz[l] - xz[l - 1]) + (yz[l] - yz[l - NPX]));
             }
             const int g = k * plane + own_xy;
 #pragma unroll
@@ -1421,12 +1499,13 @@ hipError_t step_impl(ic_ctx *c) {
     a.dt_h = (T)(p.dt / p.h);
     a.dt = (T)p.dt;
     a.fbytes = (uint32_t)((size_t)p.nx * p.ny * p.nz * sizeof(T));
+    const bool full = p.nx % TX == 0 && p.ny % TY == 0;
     const bool noise = p.kT > 0.0;
     if (noise) {
         NoiseArgs<T> na{};
         for (int i = 0; i < 9; ++i) na.out[i] = (T *)w.N[i];
         na.nx = p.nx; na.ny = p.ny; na.nz = p.nz; na.tz = c->tz;
-        na.gx = c->nblk[0]; na.gy = c->nblk[1]; na.gz = c->nblk[2];
+        na.gx = (p.nx + NTX - 1) / NTX; na.gy = (p.ny + NTY<T> - 1) / NTY<T>; na.gz = c->nblk[2];
         const double amp = 1.0 / sqrt(p.h * p.h * p.h * p.dt);
         const double an = sqrt(2.0 * p.eta * p.kT);
         const double bt = sqrt(p.zeta * p.kT / 3.0) - an / 3.0;
@@ -1437,7 +1516,8 @@ hipError_t step_impl(ic_ctx *c) {
         na.s3 = (T)sqrt(3.0);
         na.nk = NoiseKey{(uint32_t)(p.seed & 0xFFFFFFFFu), (uint32_t)(p.seed >> 32),
                          (uint32_t)(c->step & 0xFFFFFFFF), p.replica};
-        hipLaunchKernelGGL(noise_kernel<T>, dim3(nblk_all), dim3(STAGE_THREADS), 0, s, na);
+        hipLaunchKernelGGL(noise_kernel<T>, dim3(na.gx * na.gy * na.gz), dim3(NOISE_THREADS<T>), 0, s,
+                           na);
     }
     a.nmodes = c->forcing.nmodes;
     a.prof = w.prof;
@@ -1469,12 +1549,20 @@ hipError_t step_impl(ic_ctx *c) {
         }
         hipEvent_t e0 = prof_event(c), e1 = prof_event(c);
         if (e0) (void)hipEventRecord(e0, s);
-#define IC_STAGE(S, N) hipLaunchKernelGGL((stage_kernel<T, S, N>), dim3(nblk_all), dim3(STAGE_THREADS), 0, s, a)
-        if (noise) {
-            if (st == 0) IC_STAGE(0, true); else if (st == 1) IC_STAGE(1, true); else IC_STAGE(2, true);
+#define IC_STAGE(S, N, F) \
+    hipLaunchKernelGGL((stage_kernel<T, S, N, F>), dim3(nblk_all), dim3(STAGE_THREADS), 0, s, a)
+#define IC_STAGES(F)                                                                        \
+    if (noise) {                                                                            \
+        if (st == 0) IC_STAGE(0, true, F); else if (st == 1) IC_STAGE(1, true, F); else IC_STAGE(2, true, F); \
+    } else {                                                                                \
+        if (st == 0) IC_STAGE(0, false, F); else if (st == 1) IC_STAGE(1, false, F); else IC_STAGE(2, false, F); \
+    }
+        if (full) {
+            IC_STAGES(true)
         } else {
-            if (st == 0) IC_STAGE(0, false); else if (st == 1) IC_STAGE(1, false); else IC_STAGE(2, false);
+            IC_STAGES(false)
         }
+#undef IC_STAGES
 #undef IC_STAGE
         if (e1) {
             (void)hipEventRecord(e1, s);
