@@ -809,9 +809,11 @@ __device__ __forceinline__ WaveKernel wave_kernel(const Grid &G, const double q[
 }
 
 // Weight and element index of kernel point pt (0..26, x fastest) of location
-// kind (0 cell, 1+a face a).  Every lane of the wave must call it.
+// kind (0 cell, 1+a face a), and the index of the next point along axis nb
+// (-1: none).  Every lane of the wave must call it.
 __device__ __forceinline__ void wave_point(const Grid &G, const WaveKernel &k, int kind, int pt,
-                                           size_t *idx, double *w) {
+                                           size_t *idx, double *w, int nb = -1,
+                                           size_t *idx_nb = nullptr) {
     const int d[3] = {pt % 3, (pt / 3) % 3, pt / 9};
     const int n[3] = {G.nx, G.ny, G.nz};
     double wt = 1.0;
@@ -824,14 +826,10 @@ __device__ __forceinline__ void wave_point(const Grid &G, const WaveKernel &k, i
     }
     *idx = ((size_t)c[2] * G.ny + c[1]) * G.nx + c[0];
     *w = wt;
-}
-
-__device__ __forceinline__ size_t plus_one(const Grid &G, size_t i, int ax) {
-    const int x = (int)(i % G.nx), y = (int)((i / G.nx) % G.ny), z = (int)(i / ((size_t)G.nx * G.ny));
-    int c[3] = {x, y, z};
-    const int n[3] = {G.nx, G.ny, G.nz};
-    c[ax] = c[ax] + 1 == n[ax] ? 0 : c[ax] + 1;
-    return ((size_t)c[2] * G.ny + c[1]) * G.nx + c[0];
+    if (nb >= 0) {
+        c[nb] = c[nb] + 1 == n[nb] ? 0 : c[nb] + 1;
+        *idx_nb = ((size_t)c[2] * G.ny + c[1]) * G.nx + c[0];
+    }
 }
 
 // Sums over the 81 (component, point) pairs of the face kernels at q:
@@ -848,11 +846,10 @@ __device__ __forceinline__ void wave_face_sums(const Grid &G, const T *const f[4
         const bool valid = item < 81;
         const int itm = valid ? item : 0;
         const int ax = itm / 27, pt = itm % 27;
-        size_t i;
+        size_t i, j;
         double w;
-        wave_point(G, k, ax + 1, pt, &i, &w);
+        wave_point(G, k, ax + 1, pt, &i, &w, ax, &j);
         if (valid) {
-            const size_t j = plus_one(G, i, ax);
             const double rf = G.rho0 + 0.5 * ((double)f[0][i] + (double)f[0][j]);
             av[ax] += w * ((double)f[1 + ax][i] / rf);
             am[ax] += w * rf;
@@ -894,6 +891,14 @@ __global__ __launch_bounds__(256) void k_pre(const PartArgs<T> a) {
     double jv[3];
     wave_face_sums<T>(a.G, a.f, qh, jv, nullptr);         // J^{n+1/2} v^n
     const WaveKernel k = wave_kernel(a.G, qh);
+    // Omega of the first RK stage: eps V J(rho^n - rho0) at q^{n+1/2}
+    double om;
+    {
+        size_t i;
+        double w;
+        wave_point(a.G, k, 0, lane < 27 ? lane : 0, &i, &w);
+        om = wave_sum(lane < 27 ? w * (double)a.f[0][i] : 0.0);
+    }
     if (lane < 18) {
         const int ax = lane / 6, d = lane % 3;
         if ((lane % 6) < 3)
@@ -907,6 +912,7 @@ __global__ __launch_bounds__(256) void k_pre(const PartArgs<T> a) {
             a.bf[3 * p + lane - 21] = k.first;
     } else if (lane < 27) {
         const int ax = lane - 24;
+        if (ax == 0) a.omega[p] = a.eps[p] * a.V * om;
         a.qh[3 * p + ax] = qh[ax];
         a.jv_old[3 * p + ax] = jv[ax];
         a.F[3 * p + ax] = -a.ks[p] * min_image(qh[ax] - a.qeq[3 * p + ax], a.L[ax]) +
@@ -940,8 +946,8 @@ __global__ __launch_bounds__(256) void k_weights(const Grid G, int np, const dou
     }
 }
 
-// Omega_p = eps_p V J_p(rho - rho0) for the stage input density (Sec. III,
-// Eq. omega; stage pressures of App. A).
+// Omega_p = eps_p V J_p(rho - rho0) for the input density of RK stages 2 and 3
+// (Sec. III, Eq. omega; stage pressures of App. A); stage 1's comes from k_pre.
 template <typename T>
 __global__ __launch_bounds__(256) void k_omega(const PartArgs<T> a, const T *drho) {
     const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -1532,7 +1538,7 @@ hipError_t step_impl(ic_ctx *c) {
     void *const *src[3] = {U, A, B};
     void *const *dst[3] = {A, B, U};
     for (int st = 0; st < 3; ++st) {
-        if (np > 0)
+        if (np > 0 && st > 0)
             hipLaunchKernelGGL(k_omega<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa,
                                (const T *)src[st][0]);
         for (int i = 0; i < 4; ++i) {

@@ -84,6 +84,19 @@ def test_fp64_thermal_particles_ragged_multitile():
     _run_both(w, 4, check_every=1)
 
 
+def test_fp64_thermal_particles_whole_tiles():
+    # nx, ny multiples of the 32 x 16 stage tile: the whole-tile kernels
+    w = W.small_random(nx=64, ny=32, nz=20, npart=10, seed=27, kT=1e-3)
+    _run_both(w, 3, check_every=1)
+
+
+def test_fp32_whole_tiles_one_step():
+    w = W.small_random(nx=32, ny=48, nz=18, npart=6, seed=37, kT=1e-3)
+    w.drho = w.drho.astype(np.float32).astype(np.float64)
+    w.g = w.g.astype(np.float32).astype(np.float64)
+    _run_both(w, 1, prec="fp32", tol=1e-5)
+
+
 def test_fp64_deterministic_no_particles():
     w = W.small_random(nx=33, ny=17, nz=35, npart=0, seed=5, kT=0.0)
     w.modes = []
