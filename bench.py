@@ -35,6 +35,7 @@ Helper modes (they serve the profiles kept beside this file):
   --stats-summary CSV       condense a rocprofv3 --stats kernel table
   --pmc-summary F W CF CW   condense FETCH_SIZE / WRITE_SIZE passes of the bench
                             (F, W) and of the copy probe (CF, CW)
+  --instr-summary DIR       condense an SQ instruction-counter pass
 """
 from __future__ import annotations
 
@@ -269,6 +270,31 @@ def pmc_summary(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir):
             print(f"traffic_bytes_per_stage_launch_{prec}: {avg:.6g}")
 
 
+def instr_summary(dirname):
+    """Per-wave instruction counts and VALU busy fraction per kernel from an
+    SQ counter pass (SQ_WAVES, SQ_INSTS_VALU/SALU/LDS, SQ_ACTIVE_INST_VALU,
+    SQ_BUSY_CYCLES, SQ_WAIT_INST_ANY)."""
+    agg = {}
+    for fn in os.listdir(dirname):
+        if fn.endswith("counter_collection.csv"):
+            for r in csv.DictReader(open(os.path.join(dirname, fn))):
+                d = agg.setdefault(_short(r["Kernel_Name"])[:40], {})
+                d.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    print("%-40s %7s %9s %9s %8s %8s %9s" % ("kernel", "waves", "VALU/wv", "SALU/wv", "LDS/wv",
+                                             "VALUbusy", "wait/wv"))
+    for k in sorted(agg):
+        a = {c: sum(x) / len(x) for c, x in agg[k].items()}
+        w = a.get("SQ_WAVES", 0)
+        if not w or "SQ_INSTS_VALU" not in a:
+            continue
+        # 4 cycles per wave64 VALU instruction on a SIMD16; 1024 SIMDs; the
+        # busy-cycle counter sums the 32 shader engines
+        busy = a["SQ_ACTIVE_INST_VALU"] * 4 / 1024 / (a["SQ_BUSY_CYCLES"] / 32)
+        print("%-40s %7.0f %9.0f %9.0f %8.0f %7.0f%% %9.0f" % (
+            k, w, a["SQ_INSTS_VALU"] / w, a["SQ_INSTS_SALU"] / w, a["SQ_INSTS_LDS"] / w,
+            100 * busy, a["SQ_WAIT_INST_ANY"] / w))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,7 +306,10 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--stats-summary", metavar="CSV")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"))
+    ap.add_argument("--instr-summary", metavar="DIR")
     args = ap.parse_args()
+    if args.instr_summary:
+        return instr_summary(args.instr_summary)
     if args.stats_summary:
         return stats_summary(args.stats_summary)
     if args.pmc_summary:
