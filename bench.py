@@ -139,6 +139,50 @@ def run_gpu(w, prec, steps, warmup):
     return res
 
 
+def run_ensemble(prec, steps, warmup):
+    """64 thermal replicas (grid edges 32/48/64, 1-50 particles, own seeds and
+    replica ids): aggregate cell-updates/s of member-after-member eager steps
+    and of one HIP-graph launch per `steps` steps of all members."""
+    import torch
+
+    from paper_1307_0702_amd import workloads as W
+    from paper_1307_0702_amd.ensemble import Ensemble
+
+    ws = W.ensemble()
+    log(f"[bench] ensemble: {len(ws)} replicas, tuning tiles")
+    ens = Ensemble(ws, prec=prec, tune=True)
+    cells = ens.cells
+    ens.run_serial(warmup)
+    ens.synchronize()
+    t0 = time.perf_counter()
+    ens.run_serial(steps)
+    ens.synchronize()
+    t_serial = time.perf_counter() - t0
+    ens.capture(steps)
+    ens.run()
+    ens.synchronize()
+    t0 = time.perf_counter()
+    ens.run()
+    ens.synchronize()
+    t_graph = time.perf_counter() - t0
+    tiles = {}
+    for w, tz in zip(ws, ens.tiles):
+        tiles[w.fluid.nx] = tz
+    out = dict(metric="ensemble cell-updates/s", value=cells * steps / t_graph,
+               unit="cell-updates/s", n_gpus=1, steps=steps, warmup=warmup,
+               ms_per_step=t_graph * 1e3 / steps, higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f32" if prec == "fp32" else "f64", data="synthetic",
+               config=dict(workload="ensemble-64", replicas=len(ws), cells=cells,
+                           particles=sum(w.particles.n for w in ws), kT=ws[0].fluid.kT,
+                           tile_z_by_edge=tiles),
+               serial_value=cells * steps / t_serial,
+               graph_speedup=t_serial / t_graph)
+    ens.release()
+    del ens
+    torch.cuda.empty_cache()
+    return out
+
+
 def measured_traffic(prec):
     """HBM bytes per stage launch from the committed counter summary, or None
     when the summary is missing or was taken on another kernel source."""
@@ -324,6 +368,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.copy_probe:
         return copy_probe()
+    if args.workload == "ensemble-64":
+        print(json.dumps(run_ensemble("fp32" if args.prec == "both" else args.prec, args.steps,
+                                      args.warmup)), flush=True)
+        return
     log(f"[bench] building inputs for {args.workload}")
     w = make_workload(args.workload)
     fl = w.fluid

@@ -84,6 +84,7 @@ typedef struct ic_mode {
 } ic_mode;
 
 typedef struct ic_ctx ic_ctx;
+typedef struct ic_graph ic_graph;
 
 /* Validates p and creates a context bound to HIP stream `stream` (NULL =
  * default stream) on the current device.  Host only; allocates no device
@@ -134,6 +135,13 @@ int ic_set_forcing(ic_ctx *ctx, int32_t nmodes, const ic_mode *modes);
 int ic_set_step(ic_ctx *ctx, int64_t n);
 int ic_get_step(ic_ctx *ctx, int64_t *n);
 
+/* Sets / reads the z extent tz of a fluid-stage tile (4, 8, 16 or 32 planes;
+ * the default is the largest that gives at least 1024 tiles).  Results do not
+ * depend on it beyond rounding order; it trades tile count against halo
+ * re-reads.  IC_E_ARG for other values.  Any time between steps. */
+int ic_set_tile(ic_ctx *ctx, int32_t tz);
+int ic_get_tile(ic_ctx *ctx, int32_t *tz);
+
 /* Advances the bound state by nsteps IC time steps (App. A, "Temporal
  * discretization", substeps 1-7, with the three SSP-RK3 stages of the fluid
  * update).  Asynchronous.  A step whose no-slip impulse finds m_e + m_f <= 0
@@ -180,6 +188,23 @@ int ic_profile_read(ic_ctx *ctx, double *stage_ms, int64_t *launches);
 /* eps_pf from kappa_p/kappa_f: cf^2 (kappa_f/kappa_p - 1) (Sec. III, Eqs.
  * part_svel and ke). */
 double ic_eps_from_kappa_ratio(double cf, double kappa_ratio);
+
+/* Ensembles of independent runs (replicas with their own seeds or replica
+ * ids, contrast sweeps, uneven grids and particle counts).
+ * ic_graph_create captures nsteps IC steps of each of the n bound contexts
+ * into one HIP graph, one dependency chain per context, so that one launch
+ * runs the chains concurrently.  The graph holds each context's buffers,
+ * particle count, forcing and tile extent as they are at capture.  Changing
+ * any of them needs a new graph; the step counter and the drive phase live
+ * on the device and advance with each replay.  IC_E_STATE if a context is
+ * unbound or profiling, IC_E_ARG for bad arguments or a context listed twice,
+ * IC_E_HIP on a capture error.  Host only; does not run the steps.
+ * ic_graph_launch enqueues one replay on `stream` (NULL = default stream),
+ * which the caller orders with the contexts' own work; each context then
+ * stands nsteps further on.  ic_graph_destroy frees the graph. */
+int ic_graph_create(ic_ctx *const *ctxs, int32_t n, int64_t nsteps, ic_graph **out);
+int ic_graph_launch(ic_graph *graph, void *stream);
+int ic_graph_destroy(ic_graph *graph);
 
 const char *ic_strerror(int code);
 const char *ic_last_error(const ic_ctx *ctx);

@@ -29,8 +29,10 @@ int choose_tz(const ic_params &p) {
 }
 
 int nblocks_total(const ic_params &p) {
-    return tiles(p.nx, TX) * tiles(p.ny, TY) * tiles(p.nz, choose_tz(p));
+    return tiles(p.nx, TX) * tiles(p.ny, TY) * tiles(p.nz, TZ_MIN);
 }
+
+int nblocks_of(const ic_ctx *c) { return c->nblk[0] * c->nblk[1] * c->nblk[2]; }
 
 // Walks the workspace layout; with base == nullptr it only measures.
 static size_t layout(const ic_params &p, char *base, Workspace *ws) {
@@ -67,6 +69,7 @@ static size_t layout(const ic_params &p, char *base, Workspace *ws) {
     w.prof = (double *)take((size_t)IC_MAX_MODES * pmax * sizeof(double));
     w.red = (double *)take(4 * 1024 * sizeof(double));
     w.flag = (int32_t *)take(sizeof(int32_t) * 4);
+    w.st = (StepState *)take(sizeof(StepState));
     if (ws) *ws = w;
     return off;
 }
@@ -160,6 +163,17 @@ int take_flag(ic_ctx *c) {
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Ensembles: several contexts' steps captured into one HIP graph.
+// ---------------------------------------------------------------------------
+struct ic_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<ic_ctx *> ctxs;
+    int64_t nsteps = 0;
+};
+
 
 extern "C" {
 
@@ -258,6 +272,7 @@ int ic_bind(ic_ctx *c, void *drho, void *gx, void *gy, void *gz, void *workspace
     // binning counters start at zero; the scan kernel re-zeroes them after use
     if (e == hipSuccess)
         e = hipMemsetAsync(c->ws.blk_count, 0, (nblocks_total(c->p) + 1) * sizeof(int32_t), c->stream);
+    if (e == hipSuccess) e = launch_set_step(c);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "bind");
     c->bound = true;
@@ -372,6 +387,25 @@ int ic_set_step(ic_ctx *c, int64_t n) {
     if (!c) return IC_E_ARG;
     if (n < 0) return fail(c, IC_E_ARG, "step must be >= 0");
     c->step = n;
+    if (c->bound) {
+        hipError_t e = launch_set_step(c);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "set step");
+    }
+    return IC_OK;
+}
+
+int ic_set_tile(ic_ctx *c, int32_t tz) {
+    if (!c) return IC_E_ARG;
+    if (tz != 4 && tz != 8 && tz != 16 && tz != 32) return fail(c, IC_E_ARG, "tz must be 4, 8, 16 or 32");
+    c->tz = tz;
+    c->nblk[2] = (c->p.nz + tz - 1) / tz;
+    return IC_OK;
+}
+
+int ic_get_tile(ic_ctx *c, int32_t *tz) {
+    if (!c || !tz) return IC_E_ARG;
+    *tz = c->tz;
     return IC_OK;
 }
 
@@ -493,5 +527,88 @@ const char *ic_strerror(int code) {
 }
 
 const char *ic_last_error(const ic_ctx *c) { return c ? c->err.c_str() : "no context"; }
+
+int ic_graph_create(ic_ctx *const *ctxs, int32_t n, int64_t nsteps, ic_graph **out) {
+    if (!out) return IC_E_ARG;
+    *out = nullptr;
+    if (!ctxs || n <= 0 || nsteps <= 0) return IC_E_ARG;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!ctxs[i]) return IC_E_ARG;
+        if (!ctxs[i]->bound) return fail(ctxs[i], IC_E_STATE, "graph: context not bound");
+        if (ctxs[i]->profiling) return fail(ctxs[i], IC_E_STATE, "graph: profiling is on");
+        for (int32_t j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(ctxs[i], IC_E_ARG, "graph: context listed twice");
+    }
+    ic_graph *g = new (std::nothrow) ic_graph();
+    if (!g) return IC_E_ARG;
+    g->ctxs.assign(ctxs, ctxs + n);
+    g->nsteps = nsteps;
+    // one branch stream per context, forked from and joined into an origin
+    // stream that is captured (default priorities throughout)
+    hipStream_t origin = nullptr;
+    std::vector<hipStream_t> br(n, nullptr);
+    std::vector<hipEvent_t> join(n, nullptr);
+    hipEvent_t fork = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&origin, hipStreamNonBlocking);
+    for (int32_t i = 0; i < n && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    bool capturing = false;
+    if (e == hipSuccess) {
+        e = hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal);
+        capturing = e == hipSuccess;
+    }
+    if (e == hipSuccess) e = hipEventRecord(fork, origin);
+    for (int32_t i = 0; i < n && e == hipSuccess; ++i) {
+        ic_ctx *c = ctxs[i];
+        e = hipStreamWaitEvent(br[i], fork, 0);
+        const hipStream_t own = c->stream;
+        c->stream = br[i];
+        for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) e = launch_step(c);
+        c->stream = own;
+        if (e == hipSuccess) e = hipEventRecord(join[i], br[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(origin, join[i], 0);
+    }
+    if (capturing) {
+        const hipError_t e2 = hipStreamEndCapture(origin, &g->graph);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (fork) (void)hipEventDestroy(fork);
+    for (int32_t i = 0; i < n; ++i) {
+        if (join[i]) (void)hipEventDestroy(join[i]);
+        if (br[i]) (void)hipStreamDestroy(br[i]);
+    }
+    if (origin) (void)hipStreamDestroy(origin);
+    if (e != hipSuccess) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return hip_fail(ctxs[0], e, "graph capture");
+    }
+    *out = g;
+    return IC_OK;
+}
+
+int ic_graph_launch(ic_graph *g, void *stream) {
+    if (!g || !g->exec) return IC_E_ARG;
+    const hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(g->ctxs[0], e, "graph launch");
+    for (ic_ctx *c : g->ctxs) {
+        c->step += g->nsteps;
+        if (c->np > 0) c->nsamples += g->nsteps;
+    }
+    return IC_OK;
+}
+
+int ic_graph_destroy(ic_graph *g) {
+    if (!g) return IC_E_ARG;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return IC_OK;
+}
 
 }  // extern "C"

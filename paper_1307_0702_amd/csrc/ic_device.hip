@@ -236,10 +236,11 @@ struct StageArgs {
     uint32_t fbytes;  // bytes of one field (< 2^32)
     T rho0, cf2, eta, lam, inv_h, dt_h, dt, ra, rb;
     const T *noise[3]; // stochastic increment of this stage (x, y, z), NOISE only
-    // imposed pressure: sum_m mamp[m] * prof[m][coord(maxis[m])]
+    // imposed pressure: sum_m amp[m] * prof[m][coord(maxis[m])], amp at this
+    // stage's time (StepState, device)
     int nmodes;
     int maxis[IC_MAX_MODES];
-    T mamp[IC_MAX_MODES];
+    const double *amp;
     const double *prof;
     int pstride;
 };
@@ -290,7 +291,7 @@ __device__ __forceinline__ T ext_pressure_xy(const StageArgs<T> &a, int x, int y
     T s = 0;
     for (int m = 0; m < a.nmodes; ++m) {
         const int ax = a.maxis[m];
-        if (ax != 2) s += a.mamp[m] * (T)a.prof[m * a.pstride + (ax == 0 ? x : y)];
+        if (ax != 2) s += (T)a.amp[m] * (T)a.prof[m * a.pstride + (ax == 0 ? x : y)];
     }
     return s;
 }
@@ -298,7 +299,7 @@ template <typename T>
 __device__ __forceinline__ T ext_pressure_z(const StageArgs<T> &a, int z) {
     T s = 0;
     for (int m = 0; m < a.nmodes; ++m)
-        if (a.maxis[m] == 2) s += a.mamp[m] * (T)a.prof[m * a.pstride + z];
+        if (a.maxis[m] == 2) s += (T)a.amp[m] * (T)a.prof[m * a.pstride + z];
     return s;
 }
 
@@ -644,7 +645,8 @@ struct NoiseArgs {
     T *out[9];
     int nx, ny, nz, tz, gx, gy, gz;
     T dt_h, sd, st, so, s3;
-    NoiseKey nk;
+    NoiseKey nk;              // step word taken from *step at run time
+    const StepState *step;
 };
 
 // Tile of the noise kernel: 32 x NTY<T> columns (32 in FP32, 16 in FP64,
@@ -661,7 +663,9 @@ constexpr int NOISE_THREADS = NTX * NTY<T>;
 __device__ __forceinline__ int nidx(int lx, int ly) { return (ly + 1) * NPX + (lx + 1); }
 
 template <typename T>
-__global__ __launch_bounds__(NOISE_THREADS<T>) void noise_kernel(const NoiseArgs<T> a) {
+__global__ __launch_bounds__(NOISE_THREADS<T>) void noise_kernel(const NoiseArgs<T> args) {
+    NoiseArgs<T> a = args;
+    a.nk.step = args.step->cur;
     __shared__ T s_S[2][5][NPX * (NTY<T> + 2)];  // [W_A, W_B][xx, yy, xy, xz, yz], current plane
     const int nx = a.nx, ny = a.ny, nz = a.nz, tz = a.tz;
     const int plane = nx * ny;
@@ -766,6 +770,37 @@ __global__ __launch_bounds__(NOISE_THREADS<T>) void noise_kernel(const NoiseArgs
         }
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// Per-step scalars (StepState).  One wave: every lane reads the step before
+// lane 0 advances it.
+// ---------------------------------------------------------------------------
+struct DriveArgs {
+    int nmodes;
+    double dt;
+    double amp[IC_MAX_MODES], omega[IC_MAX_MODES], phase[IC_MAX_MODES];
+};
+
+__global__ __launch_bounds__(64) void k_step_begin(StepState *st, const DriveArgs d) {
+    const int lane = threadIdx.x;
+    const int64_t n = st->step;
+    // stage times t^n, t^n + dt, t^n + dt/2 (App. A, stage pressures)
+    if (lane < 3 * IC_MAX_MODES) {
+        const int stage = lane / IC_MAX_MODES, m = lane % IC_MAX_MODES;
+        const double tn = (double)n * d.dt;
+        const double t = stage == 0 ? tn : (stage == 1 ? tn + d.dt : tn + 0.5 * d.dt);
+        st->amp[stage][m] = m < d.nmodes ? d.amp[m] * sin(d.omega[m] * t + d.phase[m]) : 0.0;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        st->cur = (uint32_t)(n & 0xFFFFFFFF);
+        st->step = n + 1;
+    }
+}
+
+__global__ void k_set_step(StepState *st, int64_t n) {
+    if (threadIdx.x == 0) st->step = n;
 }
 
 // ---------------------------------------------------------------------------
@@ -1489,6 +1524,17 @@ hipError_t step_impl(ic_ctx *c) {
     const int np = c->np;
     PartArgs<T> pa = part_args<T>(c, U);
 
+    {
+        DriveArgs d{};
+        d.nmodes = c->forcing.nmodes;
+        d.dt = p.dt;
+        for (int m = 0; m < d.nmodes; ++m) {
+            d.amp[m] = c->forcing.modes[m].amp;
+            d.omega[m] = c->forcing.modes[m].omega;
+            d.phase[m] = c->forcing.modes[m].phase;
+        }
+        hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(64), 0, s, w.st, d);
+    }
     if (np > 0) {
         hipLaunchKernelGGL(k_pre<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa);
         launch_binning(c, np, w.qh);
@@ -1520,8 +1566,8 @@ hipError_t step_impl(ic_ctx *c) {
         na.st = (T)(amp * bt * sqrt(2.0));
         na.so = (T)(amp * an);
         na.s3 = (T)sqrt(3.0);
-        na.nk = NoiseKey{(uint32_t)(p.seed & 0xFFFFFFFFu), (uint32_t)(p.seed >> 32),
-                         (uint32_t)(c->step & 0xFFFFFFFF), p.replica};
+        na.nk = NoiseKey{(uint32_t)(p.seed & 0xFFFFFFFFu), (uint32_t)(p.seed >> 32), 0u, p.replica};
+        na.step = w.st;
         hipLaunchKernelGGL(noise_kernel<T>, dim3(na.gx * na.gy * na.gz), dim3(NOISE_THREADS<T>), 0, s,
                            na);
     }
@@ -1530,8 +1576,6 @@ hipError_t step_impl(ic_ctx *c) {
     a.pstride = c->prof_stride;
     for (int m = 0; m < a.nmodes; ++m) a.maxis[m] = c->forcing.modes[m].axis;
 
-    const double tn = (double)c->step * p.dt;
-    const double tst[3] = {tn, tn + p.dt, tn + 0.5 * p.dt};
     const double ra[3] = {0.0, 0.75, 1.0 / 3.0}, rb[3] = {1.0, 0.25, 2.0 / 3.0};
     void *const A[4] = {w.A[0], w.A[1], w.A[2], w.A[3]};
     void *const B[4] = {w.B[0], w.B[1], w.B[2], w.B[3]};
@@ -1549,10 +1593,7 @@ hipError_t step_impl(ic_ctx *c) {
         a.ra = (T)ra[st];
         a.rb = (T)rb[st];
         for (int i = 0; i < 3; ++i) a.noise[i] = noise ? (const T *)w.N[3 * st + i] : nullptr;
-        for (int m = 0; m < a.nmodes; ++m) {
-            const ic_mode &md = c->forcing.modes[m];
-            a.mamp[m] = (T)(md.amp * sin(md.omega * tst[st] + md.phase));
-        }
+        a.amp = w.st->amp[st];
         hipEvent_t e0 = prof_event(c), e1 = prof_event(c);
         if (e0) (void)hipEventRecord(e0, s);
 #define IC_STAGE(S, N, F) \
@@ -1671,6 +1712,11 @@ hipError_t launch_init_velocity(ic_ctx *c) {
 }
 hipError_t launch_conserved(ic_ctx *c, double *host_out) {
     return c->p.prec == IC_FP64 ? sums_impl<double>(c, host_out) : sums_impl<float>(c, host_out);
+}
+
+hipError_t launch_set_step(ic_ctx *c) {
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, c->stream, c->ws.st, (int64_t)c->step);
+    return hipGetLastError();
 }
 
 }  // namespace ic

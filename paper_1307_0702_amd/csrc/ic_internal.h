@@ -32,6 +32,21 @@ struct PartKernel {
     double *wf;      // [N][3][3] phi at the face points, per axis
 };
 
+// Per-step scalars kept on the device, so that a captured step replays with
+// the right step number and drive amplitudes: k_step_begin reads `step`,
+// publishes it in `cur` and the amplitudes of the three stage times, then
+// advances `step`.
+struct StepState {
+    int64_t step;                   // next step to run
+    uint32_t cur;                   // step in flight (low 32 bits: Philox counter word)
+    uint32_t pad;
+    double amp[3][IC_MAX_MODES];    // p_ext amplitude at t^n, t^{n+1}, t^{n+1/2}
+};
+
+// Smallest z extent of a stage block; the workspace is sized for it, so any
+// allowed extent (4, 8, 16, 32) can be chosen after creation.
+constexpr int TZ_MIN = 4;
+
 // Device workspace carved out of the caller's buffer.
 struct Workspace {
     void *A[4];          // stage buffer U~ (drho, gx, gy, gz)
@@ -51,6 +66,7 @@ struct Workspace {
     // reductions and flags
     double *red;
     int32_t *flag;
+    StepState *st;
 };
 
 struct Forcing {
@@ -88,7 +104,8 @@ namespace ic {
 size_t workspace_bytes(const ic_params &p, size_t *offsets_out = nullptr);
 int choose_tz(const ic_params &p);
 void carve_workspace(const ic_params &p, char *base, Workspace &ws);
-int nblocks_total(const ic_params &p);
+int nblocks_total(const ic_params &p);      // at the smallest z extent (workspace sizing)
+int nblocks_of(const ic_ctx *c);            // at the context's z extent
 
 // Launchers (ic_device.hip).  Each returns hipSuccess or the launch error.
 hipError_t launch_step(ic_ctx *c);
@@ -98,6 +115,7 @@ hipError_t launch_spread(ic_ctx *c, int n, const double *q, const double *f, int
                          void *field);
 hipError_t launch_init_velocity(ic_ctx *c);
 hipError_t launch_conserved(ic_ctx *c, double *host_out);
+hipError_t launch_set_step(ic_ctx *c);      // device step counter := c->step
 
 // Event pair around one stage launch when profiling (nullptr otherwise).
 hipEvent_t prof_event(ic_ctx *c);

@@ -27,6 +27,7 @@ EXPORTED = [
     "ic_get_particles", "ic_set_forcing", "ic_set_step", "ic_get_step", "ic_step",
     "ic_interpolate", "ic_spread", "ic_avg_force", "ic_conserved",
     "ic_eps_from_kappa_ratio", "ic_strerror", "ic_last_error", "ic_profile", "ic_profile_read",
+    "ic_set_tile", "ic_get_tile", "ic_graph_create", "ic_graph_launch", "ic_graph_destroy",
 ]
 
 
@@ -76,6 +77,12 @@ def load_library(path=LIB_PATH):
         "ic_profile": ([P, ctypes.c_int32], ctypes.c_int),
         "ic_profile_read": ([P, dp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "ic_last_error": ([P], ctypes.c_char_p),
+        "ic_set_tile": ([P, ctypes.c_int32], ctypes.c_int),
+        "ic_get_tile": ([P, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+        "ic_graph_create": ([ctypes.POINTER(P), ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(P)],
+                            ctypes.c_int),
+        "ic_graph_launch": ([P, P], ctypes.c_int),
+        "ic_graph_destroy": ([P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -158,6 +165,32 @@ def ic_get_step(ctx):
 
 def ic_step(ctx, nsteps):
     _check(_lib.ic_step(ctx, int(nsteps)), ctx)
+
+
+def ic_set_tile(ctx, tz):
+    _check(_lib.ic_set_tile(ctx, int(tz)), ctx)
+
+
+def ic_get_tile(ctx):
+    tz = ctypes.c_int32()
+    _check(_lib.ic_get_tile(ctx, ctypes.byref(tz)), ctx)
+    return tz.value
+
+
+def ic_graph_create(ctxs, nsteps):
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.value for c in ctxs])
+    g = ctypes.c_void_p()
+    rc = _lib.ic_graph_create(arr, len(ctxs), int(nsteps), ctypes.byref(g))
+    _check(rc, ctxs[0] if ctxs else None)
+    return g
+
+
+def ic_graph_launch(graph, stream=0):
+    _check(_lib.ic_graph_launch(graph, ctypes.c_void_p(stream)))
+
+
+def ic_graph_destroy(graph):
+    _check(_lib.ic_graph_destroy(graph))
 
 
 def ic_interpolate(ctx, n, q_dev, kind, field_dev, out_dev):
@@ -270,6 +303,12 @@ class Simulation:
 
     def step(self, n=1):
         ic_step(self.ctx, n)
+
+    def set_tile(self, tz):
+        ic_set_tile(self.ctx, tz)
+
+    def tile(self):
+        return ic_get_tile(self.ctx)
 
     def avg_force(self, reset=False):
         return ic_avg_force(self.ctx, self.np, reset)

@@ -268,6 +268,22 @@ def paper_scale_256(n=10000, seed=3):
     return Workload("paper-scale-256", fl, p, [mode], drho, g, nT)
 
 
+def ensemble(n=64, seed=4000, sizes=(32, 48, 64), max_particles=50, kT=1e-3):
+    """n independent thermal replicas: grid edge drawn from `sizes`, 1 to
+    max_particles free particles with m_p/(rho0 V) ~ U[0.5, 2] and
+    kappa_p/kappa_f ~ U[0.5, 2], noise seed seed + r and replica id r."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in range(n):
+        e = int(rng.choice(sizes))
+        npart = int(rng.integers(1, max_particles + 1))
+        fl = Fluid(e, e, e, kT=kT, seed=seed + r, replica=r)
+        p = uniform_particles(fl, npart, seed + 10000 + r, ks=0.0)
+        out.append(Workload(f"replica-{r}", fl, p, [], np.zeros(fl.shape),
+                            np.zeros((3,) + fl.shape), 0))
+    return out
+
+
 def small_random(nx=20, ny=12, nz=10, npart=6, seed=11, kT=1e-3, min_sep=None):
     """A small ragged grid with random fields and particles, for parity."""
     fl = Fluid(nx, ny, nz, kT=kT, seed=seed)
