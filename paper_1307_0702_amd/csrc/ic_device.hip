@@ -1336,27 +1336,25 @@ __global__ __launch_bounds__(STAGE_THREADS) void k_sparse(const SparseArgs<T> a)
                     add[bi] = 0.0;
                     cmp[bi] = 0;
                     if (it >= items) continue;
-                    const int ci = r0 + it / per;
-                    const int item = it % per;
-                    const int comp = item / per_comp, pt = item % per_comp;
-                    const int kind = MODE == SP_SPREAD ? a.kind : 1 + comp;
-                    const int fa = kind - 1;  // face axis, -1 for cells
-                    // point index along each axis relative to the box start
+                    const int cq = it / per;
+                    const int ci = r0 + cq;
+                    const int item = it - cq * per;
+                    const int comp = MODE == SP_SPREAD ? 0 : item / per_comp;
+                    const int pt = item - comp * per_comp;
+                    const int fa = MODE == SP_SPREAD ? a.kind - 1 : comp;  // face axis, -1: cells
+                    // point index along each axis relative to the box start;
+                    // SP_STAGE boxes span 4 points along the face axis
                     int d[3];
-                    if (MODE == SP_STAGE) {
-                        int rr = pt;  // extents 4 along the face axis, 3 along the others
-                        for (int ax = 0; ax < 3; ++ax) {
-                            const int e = ax == fa ? 4 : 3;
-                            d[ax] = rr % e;
-                            rr /= e;
-                        }
+                    if (MODE == SP_STAGE && fa == 0) {
+                        d[0] = pt % 4; d[1] = (pt / 4) % 3; d[2] = pt / 12;
+                    } else if (MODE == SP_STAGE && fa == 1) {
+                        d[0] = pt % 3; d[1] = (pt / 3) % 4; d[2] = pt / 12;
                     } else {
-                        d[0] = pt % 3;
-                        d[1] = (pt / 3) % 3;
-                        d[2] = pt / 9;
+                        d[0] = pt % 3; d[1] = (pt / 3) % 3; d[2] = pt / 9;
                     }
                     int pos[3];
                     bool in = true;
+#pragma unroll
                     for (int ax = 0; ax < 3; ++ax) {
                         int start;
                         if (MODE == SP_STAGE)
@@ -1368,33 +1366,39 @@ __global__ __launch_bounds__(STAGE_THREADS) void k_sparse(const SparseArgs<T> a)
                     }
                     if (!in) continue;
                     const size_t g = ((size_t)pos[2] * ny + pos[1]) * nx + pos[0];
-                    // weight of the cell (face == -1) or face stencil at p
-                    auto weight = [&](const int p[3], int face) {
-                        double w = 1.0;
-                        for (int ax = 0; ax < 3; ++ax) {
-                            const bool f = ax == face;
-                            int o = p[ax] - (f ? s_bf[ci][ax] : s_bc[ci][ax]);
-                            if (o < 0) o += n[ax];
-                            if (o >= 3) return 0.0;
-                            w *= f ? s_wf[ci][3 * ax + o] : s_wc[ci][3 * ax + o];
-                        }
-                        return w;
-                    };
+                    // Weights from the point offsets relative to the stencil
+                    // starts: cell weights
+                    // wc[ax][d] on the axes other than the face axis, which
+                    // are shared by every weight of the item.
+                    double po = 1.0;
+#pragma unroll
+                    for (int ax = 0; ax < 3; ++ax)
+                        if (ax != fa) po *= s_wc[ci][3 * ax + d[ax]];
                     double v;
                     if (MODE == SP_SPREAD) {
-                        v = s_v[ci][0] * weight(pos, fa) * a.inv_h3;
+                        const double w = fa < 0 ? po : po * s_wf[ci][3 * fa + d[fa]];
+                        v = s_v[ci][0] * w * a.inv_h3;
                     } else if (MODE == SP_NOSLIP) {
                         int nb[3] = {pos[0], pos[1], pos[2]};
                         nb[fa] = nb[fa] + 1 == n[fa] ? 0 : nb[fa] + 1;
                         const size_t j = ((size_t)nb[2] * ny + nb[1]) * nx + nb[0];
                         const double rf = a.rho0 + 0.5 * ((double)a.drho[g] + (double)a.drho[j]);
-                        v = rf * s_v[ci][comp] * weight(pos, fa) * a.inv_h3;
+                        v = rf * s_v[ci][comp] * (po * s_wf[ci][3 * fa + d[fa]]) * a.inv_h3;
                     } else {
-                        int nb[3] = {pos[0], pos[1], pos[2]};
-                        nb[fa] = nb[fa] + 1 == n[fa] ? 0 : nb[fa] + 1;
+                        // along the face axis the box runs bc-1 .. bc+2: the cell
+                        // at pos has offset d-1, the next cell d, the face
+                        // d - 1 + (bc - bf) in its own stencil (bc - bf is 0 or
+                        // 1 up to the period)
+                        const int dc = d[fa];
+                        int sh = s_bc[ci][fa] - s_bf[ci][fa];   // starts are stored wrapped
+                        if (sh < 0) sh += n[fa];
+                        const int of = dc - 1 + sh;
+                        const double w_pos = dc >= 1 ? po * s_wc[ci][3 * fa + dc - 1] : 0.0;
+                        const double w_nb = dc <= 2 ? po * s_wc[ci][3 * fa + dc] : 0.0;
+                        const double w_f = (of >= 0 && of <= 2) ? po * s_wf[ci][3 * fa + of] : 0.0;
                         const double om = s_v[ci][3];
-                        const double dP = om * (weight(nb, -1) - weight(pos, -1)) * a.inv_h3;
-                        const double fw = s_v[ci][comp] * weight(pos, fa) * a.inv_h3;
+                        const double dP = om * (w_nb - w_pos) * a.inv_h3;
+                        const double fw = s_v[ci][comp] * w_f * a.inv_h3;
                         v = a.b * (-a.dt_h * dP + a.dt * fw);
                     }
                     ok[bi] = true;
