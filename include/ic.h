@@ -136,9 +136,10 @@ int ic_set_step(ic_ctx *ctx, int64_t n);
 int ic_get_step(ic_ctx *ctx, int64_t *n);
 
 /* Sets / reads the z extent tz of a fluid-stage tile (4, 8, 16 or 32 planes;
- * the default is the largest that gives at least 1024 tiles).  Results do not
- * depend on it beyond rounding order; it trades tile count against halo
- * re-reads.  IC_E_ARG for other values.  Any time between steps. */
+ * the default minimises rounds of resident tiles times planes marched per
+ * tile).  Results do not depend on it beyond rounding order; it trades tile
+ * count against halo re-reads.  IC_E_ARG for other values.  Any time between
+ * steps. */
 int ic_set_tile(ic_ctx *ctx, int32_t tz);
 int ic_get_tile(ic_ctx *ctx, int32_t *tz);
 

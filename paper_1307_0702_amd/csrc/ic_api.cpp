@@ -20,12 +20,24 @@ int tiles(int n, int t) { return (n + t - 1) / t; }
 
 }  // namespace
 
-// z extent of a stage block: the largest of 32, 16, 8 planes that still gives
-// at least 1024 blocks (four per compute unit), so small grids fill the chip.
+// Default z extent of a stage block.  Blocks run in rounds of `cap` resident
+// blocks (three 512-thread blocks per compute unit in FP32, two in FP64, as
+// LDS and registers allow); a block marches tz planes plus three halo
+// planes.  The extent with the fewest rounds x planes wins (ties: the larger
+// extent, fewer halo re-reads).  ic_set_tile overrides it.
 int choose_tz(const ic_params &p) {
-    int tz = 32;
-    while (tz > 8 && tiles(p.nx, TX) * tiles(p.ny, TY) * tiles(p.nz, tz) < 1024) tz /= 2;
-    return tz;
+    const long cap = 256L * (p.prec == IC_FP64 ? 2 : 3);
+    int best = 32;
+    long best_cost = -1;
+    for (int tz = 32; tz >= TZ_MIN; tz /= 2) {
+        const long blocks = (long)tiles(p.nx, TX) * tiles(p.ny, TY) * tiles(p.nz, tz);
+        const long cost = (blocks + cap - 1) / cap * ((tz < p.nz ? tz : p.nz) + 3);
+        if (best_cost < 0 || cost < best_cost) {
+            best = tz;
+            best_cost = cost;
+        }
+    }
+    return best;
 }
 
 int nblocks_total(const ic_params &p) {
