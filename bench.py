@@ -183,6 +183,50 @@ def run_ensemble(prec, steps, warmup):
     return out
 
 
+def run_adjoint(prec, steps, warmup):
+    """Reverse mode on the deterministic 256^3 fluid (kT = 0, no particles,
+    the paper-scale drive): time of one adjoint step (stage inputs recomputed,
+    three transposed stages) against one forward step."""
+    import torch
+
+    from paper_1307_0702_amd.adjoint import Adjoint
+    from paper_1307_0702_amd.ic import Simulation
+
+    w = make_workload("paper-scale-256")
+    fl = w.fluid
+    fl.kT = 0.0
+    sim = Simulation(fl, prec=prec, max_particles=1)
+    sim.set_state(w.drho, w.g)
+    sim.set_forcing([m.as_dict() for m in w.modes])
+    adj = Adjoint(sim)
+    U = sim.U.clone()
+    lam = torch.randn_like(sim.U)
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(k):
+            fn(i)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / k
+
+    timed(lambda i: sim.step(1), warmup)
+    fwd = timed(lambda i: sim.step(1), steps)
+    timed(lambda i: adj.step(i, U, lam), warmup)
+    rev = timed(lambda i: adj.step(i, U, lam), steps)
+    ncell = fl.nx * fl.ny * fl.nz
+    out = dict(metric="adjoint cell-updates/s", value=ncell / (rev * 1e-3), unit="cell-updates/s",
+               n_gpus=1, steps=steps, warmup=warmup, ms_per_step=rev, higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f32" if prec == "fp32" else "f64",
+               data="synthetic",
+               config=dict(workload="adjoint-256", grid=[fl.nx, fl.ny, fl.nz], particles=0, kT=0.0),
+               forward_ms_per_step=fwd, adjoint_over_forward=rev / fwd,
+               finite=bool(torch.isfinite(lam).all()))
+    del adj, sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def measured_traffic(prec):
     """HBM bytes per stage launch from the committed counter summary, or None
     when the summary is missing or was taken on another kernel source."""
@@ -371,6 +415,10 @@ def main():
     if args.workload == "ensemble-64":
         print(json.dumps(run_ensemble("fp32" if args.prec == "both" else args.prec, args.steps,
                                       args.warmup)), flush=True)
+        return
+    if args.workload == "adjoint-256":
+        for prec in (["fp32", "fp64"] if args.prec == "both" else [args.prec]):
+            print(json.dumps(run_adjoint(prec, args.steps, args.warmup)), flush=True)
         return
     log(f"[bench] building inputs for {args.workload}")
     w = make_workload(args.workload)

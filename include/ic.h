@@ -207,6 +207,34 @@ int ic_graph_create(ic_ctx *const *ctxs, int32_t n, int64_t nsteps, ic_graph **o
 int ic_graph_launch(ic_graph *graph, void *stream);
 int ic_graph_destroy(ic_graph *graph);
 
+/* Reverse mode of the deterministic fluid step (kT = 0, no particles): the
+ * transpose of one IC step as a linear map of small state perturbations,
+ * for gradients of a loss of the state after N steps with respect to an
+ * earlier state and to the drive amplitudes A_m (Sec. VI pressure drive).
+ * The step is the three SSP-RK3 stages of App. A with the conservative
+ * staggered flux; its transpose runs the stages backwards.
+ * ic_adjoint_workspace_size: bytes of the extra device workspace (19 fields
+ * of the context precision plus IC_MAX_MODES x 1024 doubles).
+ * ic_bind_adjoint: binds it (caller-owned, 256-byte aligned) and zeroes the
+ * drive-gradient accumulator.  Synchronising.
+ * ic_adjoint_step: for step n taken from the state U^n = (drho, gx, gy, gz)
+ * (device, context precision, nx*ny*nz each, read only), replaces the adjoint
+ * (ldrho, lgx, lgy, lgz) = dL/dU^{n+1} (device, same layout) by dL/dU^n and
+ * adds dL/dA_m of this step to the accumulator.  The stage inputs of step n
+ * are recomputed from U^n with the forward stage kernels, so a caller keeps
+ * U^n (or re-steps to it from a checkpoint).  The bound state fields are not
+ * touched; the forward workspace is, so the call must not overlap ic_step of
+ * the same context.  IC_E_STATE if the adjoint workspace is unbound, kT != 0
+ * or particles are set; IC_E_ARG for NULL fields or n < 0.  Asynchronous.
+ * ic_adjoint_drive: grad[m] = accumulated dL/dA_m for the current drives
+ * (host, double[nmodes]), summed in a fixed order; reset != 0 zeroes the
+ * accumulator.  Synchronising. */
+int ic_adjoint_workspace_size(const ic_params *p, size_t *bytes);
+int ic_bind_adjoint(ic_ctx *ctx, void *workspace, size_t bytes);
+int ic_adjoint_step(ic_ctx *ctx, int64_t n, const void *drho, const void *gx, const void *gy,
+                    const void *gz, void *ldrho, void *lgx, void *lgy, void *lgz);
+int ic_adjoint_drive(ic_ctx *ctx, double *grad, int32_t reset);
+
 const char *ic_strerror(int code);
 const char *ic_last_error(const ic_ctx *ctx);
 

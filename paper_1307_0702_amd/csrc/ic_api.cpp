@@ -88,6 +88,28 @@ static size_t layout(const ic_params &p, char *base, Workspace *ws) {
 
 size_t workspace_bytes(const ic_params &p, size_t *) { return layout(p, nullptr, nullptr); }
 
+static size_t adj_layout(const ic_params &p, char *base, AdjWorkspace *aw) {
+    const size_t ncell = (size_t)p.nx * p.ny * p.nz;
+    const size_t esz = p.prec == IC_FP64 ? 8 : 4;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *ptr = base ? base + off : nullptr;
+        off = align_up(off + bytes);
+        return ptr;
+    };
+    AdjWorkspace w{};
+    for (int i = 0; i < 4; ++i) w.L2[i] = take(ncell * esz);
+    for (int i = 0; i < 4; ++i) w.L1[i] = take(ncell * esz);
+    for (int i = 0; i < 4; ++i) w.acc[i] = take(ncell * esz);
+    for (int i = 0; i < 7; ++i) w.mu[i] = take(ncell * esz);
+    w.partial = (double *)take((size_t)IC_MAX_MODES * ADJ_BLOCKS * sizeof(double));
+    if (aw) *aw = w;
+    return off;
+}
+
+size_t adjoint_workspace_bytes(const ic_params &p) { return adj_layout(p, nullptr, nullptr); }
+void carve_adjoint(const ic_params &p, char *base, AdjWorkspace &aw) { adj_layout(p, base, &aw); }
+
 void carve_workspace(const ic_params &p, char *base, Workspace &ws) { layout(p, base, &ws); }
 
 hipEvent_t prof_event(ic_ctx *c) {
@@ -201,6 +223,7 @@ int ic_create(const ic_params *p, void *stream, ic_ctx **out) {
     c->device = 0;
     (void)hipGetDevice(&c->device);
     c->bound = false;
+    c->adj_bound = false;
     c->np = 0;
     c->step = 0;
     c->nsamples = 0;
@@ -539,6 +562,66 @@ const char *ic_strerror(int code) {
 }
 
 const char *ic_last_error(const ic_ctx *c) { return c ? c->err.c_str() : "no context"; }
+
+int ic_adjoint_workspace_size(const ic_params *p, size_t *bytes) {
+    if (!bytes) return IC_E_ARG;
+    const int rc = check_params(p, nullptr);
+    if (rc != IC_OK) return rc;
+    *bytes = adjoint_workspace_bytes(*p);
+    return IC_OK;
+}
+
+int ic_bind_adjoint(ic_ctx *c, void *workspace, size_t bytes) {
+    if (!c) return IC_E_ARG;
+    if (!workspace) return fail(c, IC_E_ARG, "NULL adjoint workspace");
+    if (((uintptr_t)workspace & 255) != 0) return fail(c, IC_E_ARG, "adjoint workspace not 256-byte aligned");
+    if (bytes < adjoint_workspace_bytes(c->p)) return fail(c, IC_E_ARG, "adjoint workspace too small");
+    carve_adjoint(c->p, (char *)workspace, c->adj);
+    hipError_t e = hipMemsetAsync(c->adj.partial, 0, (size_t)IC_MAX_MODES * ADJ_BLOCKS * sizeof(double),
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "bind adjoint");
+    c->adj_bound = true;
+    return IC_OK;
+}
+
+int ic_adjoint_step(ic_ctx *c, int64_t n, const void *drho, const void *gx, const void *gy,
+                    const void *gz, void *ldrho, void *lgx, void *lgy, void *lgz) {
+    int rc = check_bound(c);
+    if (rc != IC_OK) return rc;
+    if (!c->adj_bound) return fail(c, IC_E_STATE, "adjoint workspace not bound");
+    if (c->p.kT != 0.0) return fail(c, IC_E_STATE, "adjoint needs kT = 0");
+    if (c->np != 0) return fail(c, IC_E_STATE, "adjoint needs a particle-free context");
+    if (n < 0) return fail(c, IC_E_ARG, "step must be >= 0");
+    if (!drho || !gx || !gy || !gz || !ldrho || !lgx || !lgy || !lgz)
+        return fail(c, IC_E_ARG, "NULL field");
+    const void *const Un[4] = {drho, gx, gy, gz};
+    void *const lam[4] = {ldrho, lgx, lgy, lgz};
+    hipError_t e = launch_adjoint_step(c, n, Un, lam);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint step");
+    return IC_OK;
+}
+
+int ic_adjoint_drive(ic_ctx *c, double *grad, int32_t reset) {
+    if (!c || !grad) return IC_E_ARG;
+    if (!c->adj_bound) return fail(c, IC_E_STATE, "adjoint workspace not bound");
+    std::vector<double> part((size_t)IC_MAX_MODES * ADJ_BLOCKS);
+    hipError_t e = hipMemcpyAsync(part.data(), c->adj.partial, part.size() * sizeof(double),
+                                  hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint drive read");
+    for (int m = 0; m < c->forcing.nmodes; ++m) {
+        double sum = 0.0;
+        for (int b = 0; b < ADJ_BLOCKS; ++b) sum += part[(size_t)m * ADJ_BLOCKS + b];
+        grad[m] = sum;
+    }
+    if (reset) {
+        e = hipMemsetAsync(c->adj.partial, 0, part.size() * sizeof(double), c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "adjoint drive reset");
+    }
+    return IC_OK;
+}
 
 int ic_graph_create(ic_ctx *const *ctxs, int32_t n, int64_t nsteps, ic_graph **out) {
     if (!out) return IC_E_ARG;

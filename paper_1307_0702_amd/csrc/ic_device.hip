@@ -1421,6 +1421,233 @@ __global__ __launch_bounds__(STAGE_THREADS) void k_sparse(const SparseArgs<T> a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint (reverse mode) of one deterministic, particle-free RK3 step: the
+// transpose of the stage increment Delta(U) (conservative staggered flux of
+// the stage kernel, App. A) applied to an adjoint state lambda, one cell per
+// thread, neighbours read through the caches.
+//   pass 1: mu_g (incl. the v = g / rho_face chain), mu_rf = d/d rho_face,
+//           mu_p = sum of the centre-flux adjoints (drive gradient)
+//   pass 2: mu_rho = c_f^2 mu_p + (mu_rf[i] + mu_rf[i-a]) / 2, and the RK
+//           combination out = cs (lambda + mu), acc += ds lambda
+// ---------------------------------------------------------------------------
+template <typename T>
+struct AdjArgs {
+    const T *U[4];      // stage input (drho, gx, gy, gz)
+    const T *lam[4];    // adjoint of the stage output
+    T *mu[7];           // mu_gx, mu_gy, mu_gz, mu_rf x3, mu_p
+    int nx, ny, nz;
+    double rho0, cf2, eta, lam_b, k, inv_h;   // lam_b = zeta - 2 eta / 3, k = dt / h
+};
+
+struct Cell {
+    int x, y, z, nx, ny, nz;
+    __device__ __forceinline__ size_t at(int a, int s) const {
+        int c[3] = {x, y, z};
+        const int n[3] = {nx, ny, nz};
+        c[a] += s;
+        if (c[a] < 0) c[a] += n[a];
+        if (c[a] >= n[a]) c[a] -= n[a];
+        return ((size_t)c[2] * ny + c[1]) * nx + c[0];
+    }
+    __device__ __forceinline__ size_t at2(int a, int s, int b, int t) const {
+        int c[3] = {x, y, z};
+        const int n[3] = {nx, ny, nz};
+        c[a] += s;
+        c[b] += t;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (c[d] < 0) c[d] += n[d];
+            if (c[d] >= n[d]) c[d] -= n[d];
+        }
+        return ((size_t)c[2] * ny + c[1]) * nx + c[0];
+    }
+};
+
+template <typename T>
+struct AdjView {
+    const AdjArgs<T> &a;
+    __device__ double rf(int ax, size_t i, size_t ip) const {
+        return a.rho0 + 0.5 * ((double)a.U[0][i] + (double)a.U[0][ip]);
+    }
+    // v_ax at the cell whose flat index is i (its +ax neighbour is ip)
+    __device__ double v(int ax, size_t i, size_t ip) const {
+        return (double)a.U[1 + ax][i] / rf(ax, i, ip);
+    }
+    __device__ double g(int ax, size_t i) const { return (double)a.U[1 + ax][i]; }
+    __device__ double lg(int ax, size_t i) const { return (double)a.lam[1 + ax][i]; }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_pass1(const AdjArgs<T> a) {
+    const size_t ncell = (size_t)a.nx * a.ny * a.nz;
+    const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ncell) return;
+    const Cell C{(int)(j % a.nx), (int)((j / a.nx) % a.ny), (int)(j / ((size_t)a.nx * a.ny)),
+                 a.nx, a.ny, a.nz};
+    const AdjView<T> W{a};
+    const double k = a.k, eta = a.eta, ih = a.inv_h;
+    // v_ax at cell C shifted by s along sa (and t along sb)
+    auto vat = [&](int ax, int sa, int s, int sb, int t) {
+        const size_t i = C.at2(sa, s, sb, t);
+        const Cell D{(int)(i % a.nx), (int)((i / a.nx) % a.ny), (int)(i / ((size_t)a.nx * a.ny)),
+                     a.nx, a.ny, a.nz};
+        return W.v(ax, i, D.at(ax, 1));
+    };
+    auto gat = [&](int ax, int sa, int s, int sb, int t) { return W.g(ax, C.at2(sa, s, sb, t)); };
+    auto lgat = [&](int ax, int sa, int s, int sb, int t) { return W.lg(ax, C.at2(sa, s, sb, t)); };
+    // Every term below names its neighbour offsets explicitly; lgat(c, sa, s,
+    // sb, t) is lambda_g_c at the cell shifted s along sa and t along sb.
+    double mu_p = 0.0;
+    // mu_p at a shifted cell: sum over ax of -k (lg_ax[i - e_ax] - lg_ax[i])
+    auto mup_at = [&](int sa, int s) {
+        double m = 0.0;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax)
+            m += -k * (lgat(ax, sa, s, ax, -1) - lgat(ax, sa, s, ax, 0));
+        return m;
+    };
+    mu_p = mup_at(0, 0);
+    double mug[3], muv[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        // mass: -k (lr[j] - lr[j+ax])
+        const double lr0 = (double)a.lam[0][j], lr1 = (double)a.lam[0][C.at(ax, 1)];
+        double mgv = -k * (lr0 - lr1);
+        double mvv = 0.0;
+        // centre flux C_ax at cells j and j+ax: muC_ax(i) = -k (lg_ax[i-ax] - lg_ax[i])
+        const double mC0 = -k * (lgat(ax, ax, -1, ax, 0) - lgat(ax, ax, 0, ax, 0));
+        const double mC1 = -k * (lgat(ax, ax, 0, ax, 0) - lgat(ax, ax, 1, ax, 0));
+        // B_ax(i) = v_ax(i) + v_ax(i-ax); A_ax(i) = (g_ax(i) + g_ax(i-ax)) / 4
+        const double v0 = vat(ax, ax, 0, ax, 0), vm = vat(ax, ax, -1, ax, 0), vp = vat(ax, ax, 1, ax, 0);
+        const double g0 = gat(ax, ax, 0, ax, 0), gm = gat(ax, ax, -1, ax, 0), gp = gat(ax, ax, 1, ax, 0);
+        mgv += 0.25 * (v0 + vm) * mC0 + 0.25 * (vp + v0) * mC1;
+        mvv += 0.25 * (g0 + gm) * mC0 + 0.25 * (gp + g0) * mC1;
+        mvv += -2.0 * eta * ih * (mC0 - mC1);
+        // bulk: mu_div(i) = -lam_b mu_p(i); mu_v_ax += (mu_div(j) - mu_div(j+ax)) / h
+        mvv += -a.lam_b * (mu_p - mup_at(ax, 1)) * ih;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if (b == ax) continue;
+            // edge flux E_{ax b}(i) = (g_ax(i) + g_ax(i+b)) (v_b(i) + v_b(i+ax)) / 4 - visc;
+            // muE_{ax b}(i) = -k (lg_ax(i) - lg_ax(i+b)); it reaches g_ax at j from
+            // i = j and i = j - b
+            const double mE0 = -k * (lgat(ax, b, 0, b, 0) - lgat(ax, b, 1, b, 0));
+            const double mEm = -k * (lgat(ax, b, -1, b, 0) - lgat(ax, b, 0, b, 0));
+            const double Q0 = vat(b, b, 0, ax, 0) + vat(b, ax, 1, b, 0);
+            const double Qm = vat(b, b, -1, ax, 0) + vat(b, b, -1, ax, 1);
+            mgv += 0.25 * Q0 * mE0 + 0.25 * Qm * mEm;
+            // viscous part of E_{ax b} as a function of v_ax: -eta/h (v_ax(i+b) - v_ax(i))
+            mvv += -eta * ih * (mEm - mE0);
+            // edge flux E_{b ax}(i) = (g_b(i) + g_b(i+ax)) (v_ax(i) + v_ax(i+b)) / 4 - visc,
+            // muE_{b ax}(i) = -k (lg_b(i) - lg_b(i+ax)); it reaches v_ax at j from
+            // i = j and i = j - b
+            const double mF0 = -k * (lgat(b, ax, 0, ax, 0) - lgat(b, ax, 1, ax, 0));
+            const double mFm = -k * (lgat(b, b, -1, ax, 0) - lgat(b, b, -1, ax, 1));
+            const double P0 = gat(b, ax, 0, ax, 0) + gat(b, ax, 1, ax, 0);
+            const double Pm = gat(b, b, -1, ax, 0) + gat(b, b, -1, ax, 1);
+            mvv += 0.25 * P0 * mF0 + 0.25 * Pm * mFm;
+            // viscous part of E_{b ax} as a function of v_ax: -eta/h (v_ax(i+b) - v_ax(i))
+            mvv += -eta * ih * (mFm - mF0);
+        }
+        // v_ax = g_ax / rf_ax
+        const double rfj = W.rf(ax, j, C.at(ax, 1));
+        mug[ax] = mgv + mvv / rfj;
+        muv[ax] = -mvv * (g0 / rfj) / rfj;   // mu_rf
+    }
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        a.mu[ax][j] = (T)mug[ax];
+        a.mu[3 + ax][j] = (T)muv[ax];
+    }
+    a.mu[6][j] = (T)mu_p;
+}
+
+// RK combination of the reversed stages (U^{n+1} = U^n/3 + 2/3 (U2 + D(U2)),
+// U2 = 3/4 U^n + 1/4 (U1 + D(U1)), U1 = U^n + D(U^n)):
+//   ADJ_FIRST (stage 3): out = cs (lam + mu), acc  = ds lam
+//   ADJ_MID   (stage 2): out = cs (lam + mu), acc += ds lam
+//   ADJ_LAST  (stage 1): out = acc + cs (lam + mu)
+enum AdjMode { ADJ_FIRST = 0, ADJ_MID = 1, ADJ_LAST = 2 };
+
+template <typename T>
+struct AdjCombine {
+    const T *lam[4];
+    const T *mu[7];
+    T *out[4];
+    T *acc[4];
+    int nx, ny, nz;
+    double cf2, cs, ds;
+    int mode;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_pass2(const AdjCombine<T> a) {
+    const size_t ncell = (size_t)a.nx * a.ny * a.nz;
+    const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ncell) return;
+    const Cell C{(int)(j % a.nx), (int)((j / a.nx) % a.ny), (int)(j / ((size_t)a.nx * a.ny)),
+                 a.nx, a.ny, a.nz};
+    double mu[4];
+    mu[0] = a.cf2 * (double)a.mu[6][j];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        mu[0] += 0.5 * ((double)a.mu[3 + ax][j] + (double)a.mu[3 + ax][C.at(ax, -1)]);
+        mu[1 + ax] = (double)a.mu[ax][j];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const double l = (double)a.lam[c][j];
+        const double o = a.cs * (l + mu[c]);
+        if (a.mode == ADJ_LAST) {
+            a.out[c][j] = (T)((double)a.acc[c][j] + o);
+        } else {
+            a.out[c][j] = (T)o;
+            const double prev = a.mode == ADJ_MID ? (double)a.acc[c][j] : 0.0;
+            a.acc[c][j] = (T)(prev + a.ds * l);
+        }
+    }
+}
+
+struct DriveCoef {
+    int axis[IC_MAX_MODES];
+    double c[IC_MAX_MODES];
+};
+
+// partial[m][block] += coef[m] * sum over the block's cells of mu_p prof_m
+// (fixed block order: the host adds the partials in order)
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_drive(const T *mu_p, int nx, int ny, int nz, int nmodes,
+                                                   const double *prof, int pstride, DriveCoef coef,
+                                                   double *partial) {
+    __shared__ double s[IC_MAX_MODES][256];
+    const size_t n = (size_t)nx * ny * nz;
+    double acc[IC_MAX_MODES];
+#pragma unroll
+    for (int m = 0; m < IC_MAX_MODES; ++m) acc[m] = 0.0;
+    for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(j % nx), y = (int)((j / nx) % ny), z = (int)(j / ((size_t)nx * ny));
+        const double mp = (double)mu_p[j];
+#pragma unroll
+        for (int m = 0; m < IC_MAX_MODES; ++m) {
+            if (m >= nmodes) break;
+            const int ax = coef.axis[m];
+            acc[m] += mp * prof[m * pstride + (ax == 0 ? x : (ax == 1 ? y : z))];
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < IC_MAX_MODES; ++m) s[m][threadIdx.x] = acc[m];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int m = 0; m < nmodes; ++m) s[m][threadIdx.x] += s[m][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int m = 0; m < nmodes; ++m) partial[m * gridDim.x + blockIdx.x] += coef.c[m] * s[m][0];
+}
+
 // FP64 block partial sums of the four fields (deterministic order).
 template <typename T>
 __global__ __launch_bounds__(256) void k_sums(const T *f0, const T *f1, const T *f2, const T *f3,
@@ -1697,6 +1924,127 @@ hipError_t sums_impl(ic_ctx *c, double *host4) {
 }
 
 }  // namespace
+
+// Reverse of one deterministic particle-free step (see k_adj_pass1).  The
+// stage inputs U1, U2 of step n are recomputed from U^n with the forward
+// stage kernels into the workspace stage buffers.
+template <typename T>
+hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *const lam[4]) {
+    const ic_params &p = c->p;
+    hipStream_t s = c->stream;
+    const Workspace &w = c->ws;
+    const AdjWorkspace &aw = c->adj;
+    const size_t ncell = (size_t)p.nx * p.ny * p.nz;
+    const unsigned nb = (unsigned)((ncell + 255) / 256);
+    const unsigned nblk_all = (unsigned)(c->nblk[0] * c->nblk[1] * c->nblk[2]);
+    const bool full = p.nx % TX == 0 && p.ny % TY == 0;
+
+    // stage inputs of step n
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, w.st, (int64_t)n);
+    DriveArgs d{};
+    d.nmodes = c->forcing.nmodes;
+    d.dt = p.dt;
+    for (int m = 0; m < d.nmodes; ++m) {
+        d.amp[m] = c->forcing.modes[m].amp;
+        d.omega[m] = c->forcing.modes[m].omega;
+        d.phase[m] = c->forcing.modes[m].phase;
+    }
+    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(64), 0, s, w.st, d);
+    StageArgs<T> a{};
+    a.nx = p.nx; a.ny = p.ny; a.nz = p.nz; a.tz = c->tz;
+    a.gx = c->nblk[0]; a.gy = c->nblk[1]; a.gz = c->nblk[2];
+    a.rho0 = (T)p.rho0;
+    a.cf2 = (T)(p.cf * p.cf);
+    a.eta = (T)p.eta;
+    a.lam = (T)(p.zeta - 2.0 * p.eta / 3.0);
+    a.inv_h = (T)(1.0 / p.h);
+    a.dt_h = (T)(p.dt / p.h);
+    a.dt = (T)p.dt;
+    a.fbytes = (uint32_t)(ncell * sizeof(T));
+    a.nmodes = c->forcing.nmodes;
+    a.prof = w.prof;
+    a.pstride = c->prof_stride;
+    for (int m = 0; m < a.nmodes; ++m) a.maxis[m] = c->forcing.modes[m].axis;
+    for (int i = 0; i < 4; ++i) {
+        a.in[i] = (const T *)Un[i];
+        a.un[i] = (const T *)Un[i];
+        a.out[i] = (T *)w.A[i];
+    }
+    a.ra = (T)0.0;
+    a.rb = (T)1.0;
+    a.amp = w.st->amp[0];
+    if (full)
+        hipLaunchKernelGGL((stage_kernel<T, 0, false, true>), dim3(nblk_all), dim3(STAGE_THREADS), 0, s, a);
+    else
+        hipLaunchKernelGGL((stage_kernel<T, 0, false, false>), dim3(nblk_all), dim3(STAGE_THREADS), 0, s, a);
+    for (int i = 0; i < 4; ++i) {
+        a.in[i] = (const T *)w.A[i];
+        a.out[i] = (T *)w.B[i];
+    }
+    a.ra = (T)0.75;
+    a.rb = (T)0.25;
+    a.amp = w.st->amp[1];
+    if (full)
+        hipLaunchKernelGGL((stage_kernel<T, 1, false, true>), dim3(nblk_all), dim3(STAGE_THREADS), 0, s, a);
+    else
+        hipLaunchKernelGGL((stage_kernel<T, 1, false, false>), dim3(nblk_all), dim3(STAGE_THREADS), 0, s, a);
+
+    // reverse the three stages: (stage input, adjoint in, adjoint out, cs, ds)
+    const double tn = (double)n * p.dt;
+    const double ts[3] = {tn, tn + p.dt, tn + 0.5 * p.dt};
+    const void *const *Uin[3] = {Un, (const void *const *)w.A, (const void *const *)w.B};
+    void *const *Lout[3] = {lam, aw.L1, aw.L2};
+    const void *const *Lin[3] = {(const void *const *)aw.L1, (const void *const *)aw.L2,
+                                 (const void *const *)lam};
+    const double cs[3] = {1.0, 0.25, 2.0 / 3.0}, ds[3] = {1.0, 0.75, 1.0 / 3.0};
+    for (int st = 2; st >= 0; --st) {
+        AdjArgs<T> x{};
+        for (int i = 0; i < 4; ++i) {
+            x.U[i] = (const T *)Uin[st][i];
+            x.lam[i] = (const T *)Lin[st][i];
+        }
+        for (int i = 0; i < 7; ++i) x.mu[i] = (T *)aw.mu[i];
+        x.nx = p.nx; x.ny = p.ny; x.nz = p.nz;
+        x.rho0 = p.rho0;
+        x.cf2 = p.cf * p.cf;
+        x.eta = p.eta;
+        x.lam_b = p.zeta - 2.0 * p.eta / 3.0;
+        x.k = p.dt / p.h;
+        x.inv_h = 1.0 / p.h;
+        hipLaunchKernelGGL(k_adj_pass1<T>, dim3(nb), dim3(256), 0, s, x);
+        if (c->forcing.nmodes > 0) {
+            DriveCoef dc{};
+            for (int m = 0; m < c->forcing.nmodes; ++m) {
+                const ic_mode &md = c->forcing.modes[m];
+                dc.axis[m] = md.axis;
+                dc.c[m] = cs[st] * sin(md.omega * ts[st] + md.phase);
+            }
+            hipLaunchKernelGGL(k_adj_drive<T>, dim3(ADJ_BLOCKS), dim3(256), 0, s, (const T *)aw.mu[6],
+                               p.nx, p.ny, p.nz, c->forcing.nmodes, (const double *)w.prof,
+                               c->prof_stride, dc, aw.partial);
+        }
+        AdjCombine<T> cmb{};
+        for (int i = 0; i < 4; ++i) {
+            cmb.lam[i] = (const T *)Lin[st][i];
+            cmb.out[i] = (T *)Lout[st][i];
+            cmb.acc[i] = (T *)aw.acc[i];
+        }
+        for (int i = 0; i < 7; ++i) cmb.mu[i] = (const T *)aw.mu[i];
+        cmb.nx = p.nx; cmb.ny = p.ny; cmb.nz = p.nz;
+        cmb.cf2 = p.cf * p.cf;
+        cmb.cs = cs[st];
+        cmb.ds = ds[st];
+        cmb.mode = st == 2 ? ADJ_FIRST : (st == 1 ? ADJ_MID : ADJ_LAST);
+        hipLaunchKernelGGL(k_adj_pass2<T>, dim3(nb), dim3(256), 0, s, cmb);
+    }
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, w.st, (int64_t)c->step);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(ic_ctx *c, int64_t n, const void *const Un[4], void *const lam[4]) {
+    return c->p.prec == IC_FP64 ? adjoint_impl<double>(c, n, Un, lam)
+                                : adjoint_impl<float>(c, n, Un, lam);
+}
 
 hipError_t launch_step(ic_ctx *c) {
     return c->p.prec == IC_FP64 ? step_impl<double>(c) : step_impl<float>(c);

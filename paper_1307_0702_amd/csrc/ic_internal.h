@@ -69,6 +69,17 @@ struct Workspace {
     StepState *st;
 };
 
+// Adjoint workspace (ic_bind_adjoint): adjoint stage states, the
+// accumulator of dL/dU^n, the transposed-increment fields and the per-block
+// partial sums of the drive-amplitude gradient.
+constexpr int ADJ_BLOCKS = 1024;
+struct AdjWorkspace {
+    void *L2[4], *L1[4], *acc[4], *mu[7];
+    double *partial;   // [IC_MAX_MODES][ADJ_BLOCKS]
+};
+size_t adjoint_workspace_bytes(const ic_params &p);
+void carve_adjoint(const ic_params &p, char *base, AdjWorkspace &aw);
+
 struct Forcing {
     int nmodes;
     ic_mode modes[IC_MAX_MODES];
@@ -97,6 +108,9 @@ struct ic_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
     double prof_ms;
     int64_t prof_launches;
+    // reverse mode (ic_bind_adjoint)
+    bool adj_bound;
+    ic::AdjWorkspace adj;
 };
 
 namespace ic {
@@ -116,6 +130,9 @@ hipError_t launch_spread(ic_ctx *c, int n, const double *q, const double *f, int
 hipError_t launch_init_velocity(ic_ctx *c);
 hipError_t launch_conserved(ic_ctx *c, double *host_out);
 hipError_t launch_set_step(ic_ctx *c);      // device step counter := c->step
+// Reverse of step n from the state U^n (device fields): lam (device, in:
+// dL/dU^{n+1}, out: dL/dU^n); drive gradient added to the adjoint partials.
+hipError_t launch_adjoint_step(ic_ctx *c, int64_t n, const void *const Un[4], void *const lam[4]);
 
 // Event pair around one stage launch when profiling (nullptr otherwise).
 hipEvent_t prof_event(ic_ctx *c);

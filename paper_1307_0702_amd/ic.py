@@ -28,6 +28,7 @@ EXPORTED = [
     "ic_interpolate", "ic_spread", "ic_avg_force", "ic_conserved",
     "ic_eps_from_kappa_ratio", "ic_strerror", "ic_last_error", "ic_profile", "ic_profile_read",
     "ic_set_tile", "ic_get_tile", "ic_graph_create", "ic_graph_launch", "ic_graph_destroy",
+    "ic_adjoint_workspace_size", "ic_bind_adjoint", "ic_adjoint_step", "ic_adjoint_drive",
 ]
 
 
@@ -83,6 +84,11 @@ def load_library(path=LIB_PATH):
                             ctypes.c_int),
         "ic_graph_launch": ([P, P], ctypes.c_int),
         "ic_graph_destroy": ([P], ctypes.c_int),
+        "ic_adjoint_workspace_size": ([ctypes.POINTER(ic_params), ctypes.POINTER(ctypes.c_size_t)],
+                                      ctypes.c_int),
+        "ic_bind_adjoint": ([P, P, ctypes.c_size_t], ctypes.c_int),
+        "ic_adjoint_step": ([P, ctypes.c_int64, P, P, P, P, P, P, P, P], ctypes.c_int),
+        "ic_adjoint_drive": ([P, dp, ctypes.c_int32], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -191,6 +197,30 @@ def ic_graph_launch(graph, stream=0):
 
 def ic_graph_destroy(graph):
     _check(_lib.ic_graph_destroy(graph))
+
+
+def ic_adjoint_workspace_size(params):
+    n = ctypes.c_size_t()
+    _check(_lib.ic_adjoint_workspace_size(ctypes.byref(params), ctypes.byref(n)))
+    return n.value
+
+
+def ic_bind_adjoint(ctx, ws, nbytes):
+    _check(_lib.ic_bind_adjoint(ctx, _ptr(ws), int(nbytes)), ctx)
+
+
+def ic_adjoint_step(ctx, n, U, lam):
+    """U: the four state fields of step n (device); lam: the four adjoint
+    fields (device), dL/dU^{n+1} in, dL/dU^n out."""
+    _check(_lib.ic_adjoint_step(ctx, int(n), *[_ptr(x) for x in U], *[_ptr(x) for x in lam]), ctx)
+
+
+def ic_adjoint_drive(ctx, nmodes, reset=False):
+    """dL/dA_m of the context's first nmodes drives (it holds at most
+    IC_MAX_MODES)."""
+    out = (ctypes.c_double * IC_MAX_MODES)()
+    _check(_lib.ic_adjoint_drive(ctx, out, int(bool(reset))), ctx)
+    return np.array(list(out)[:int(nmodes)])
 
 
 def ic_interpolate(ctx, n, q_dev, kind, field_dev, out_dev):
