@@ -62,7 +62,8 @@ static size_t layout(const ic_params &p, char *base, Workspace *ws) {
     Workspace w{};
     for (int i = 0; i < 4; ++i) w.A[i] = take(ncell * esz);
     for (int i = 0; i < 4; ++i) w.B[i] = take(ncell * esz);
-    for (int i = 0; i < 9; ++i) w.N[i] = p.kT > 0.0 ? take(ncell * esz) : nullptr;
+    for (int k = 0; k < 2; ++k)
+        for (int i = 0; i < 9; ++i) w.N[k][i] = p.kT > 0.0 ? take(ncell * esz) : nullptr;
     auto d3 = [&]() { return (double *)take(3 * N * sizeof(double)); };
     auto d1 = [&]() { return (double *)take(N * sizeof(double)); };
     w.q = d3(); w.u = d3(); w.me = d1(); w.eps = d1(); w.ks = d1(); w.qeq = d3(); w.fext = d3();
@@ -238,6 +239,8 @@ int ic_create(const ic_params *p, void *stream, ic_ctx **out) {
     c->profiling = false;
     c->prof_ms = 0.0;
     c->prof_launches = 0;
+    c->side = nullptr;
+    c->ev_fork = c->ev_part = c->ev_noise = nullptr;
     *out = c;
     return IC_OK;
 }
@@ -250,6 +253,12 @@ int ic_destroy(ic_ctx *c) {
         (void)hipEventDestroy(pr.second);
     }
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->side) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamDestroy(c->side);
+    }
+    for (hipEvent_t e : {c->ev_fork, c->ev_part, c->ev_noise})
+        if (e) (void)hipEventDestroy(e);
     delete c;
     return IC_OK;
 }
@@ -295,6 +304,22 @@ int ic_bind(ic_ctx *c, void *drho, void *gx, void *gy, void *gz, void *workspace
     if (!drho || !gx || !gy || !gz || !workspace) return fail(c, IC_E_ARG, "NULL buffer");
     if (((uintptr_t)workspace & 255) != 0) return fail(c, IC_E_ARG, "workspace not 256-byte aligned");
     if (workspace_bytes_ < workspace_bytes(c->p)) return fail(c, IC_E_ARG, "workspace too small");
+    if (!c->side) {
+        // side stream and its events, created with the first binding
+        hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_part, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_noise, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (c->side) (void)hipStreamDestroy(c->side);
+            for (hipEvent_t *ev : {&c->ev_fork, &c->ev_part, &c->ev_noise}) {
+                if (*ev) (void)hipEventDestroy(*ev);
+                *ev = nullptr;
+            }
+            c->side = nullptr;
+            return hip_fail(c, e, "bind: side stream");
+        }
+    }
     c->f[0] = drho;
     c->f[1] = gx;
     c->f[2] = gy;
@@ -455,7 +480,7 @@ int ic_step(ic_ctx *c, int64_t nsteps) {
     if (rc != IC_OK) return rc;
     if (nsteps < 0) return fail(c, IC_E_ARG, "nsteps < 0");
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipError_t e = launch_step(c);
+        hipError_t e = launch_step(c, true, s == 0, s == nsteps - 1);
         if (e != hipSuccess) return hip_fail(c, e, "step launch");
         c->step += 1;
         if (c->np > 0) c->nsamples += 1;
@@ -661,7 +686,9 @@ int ic_graph_create(ic_ctx *const *ctxs, int32_t n, int64_t nsteps, ic_graph **o
         e = hipStreamWaitEvent(br[i], fork, 0);
         const hipStream_t own = c->stream;
         c->stream = br[i];
-        for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) e = launch_step(c);
+        // single-stream steps: a second stream forked from the branch stream
+        // would nest one capture join inside another
+        for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) e = launch_step(c, false, true, true);
         c->stream = own;
         if (e == hipSuccess) e = hipEventRecord(join[i], br[i]);
         if (e == hipSuccess) e = hipStreamWaitEvent(origin, join[i], 0);

@@ -235,7 +235,10 @@ struct StageArgs {
     int nx, ny, nz, tz, gx, gy, gz;
     uint32_t fbytes;  // bytes of one field (< 2^32)
     T rho0, cf2, eta, lam, inv_h, dt_h, dt, ra, rb;
-    const T *noise[3]; // stochastic increment of this stage (x, y, z), NOISE only
+    // stochastic increment of this stage (x, y, z) in the two noise sets,
+    // NOISE only; step n reads set n & 1 (StepState.cur)
+    const T *noise[2][3];
+    const StepState *st;
     // imposed pressure: sum_m amp[m] * prof[m][coord(maxis[m])], amp at this
     // stage's time (StepState, device)
     int nmodes;
@@ -349,7 +352,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void stage_kernel(c
     }
     if (NOISE) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) rnn[c] = make_rsrc(a.noise[c], a.fbytes);
+        for (int c = 0; c < 3; ++c)
+            rnn[c] = make_rsrc((a.st->cur & 1u) ? a.noise[1][c] : a.noise[0][c], a.fbytes);
     }
     auto soff = [&](int p) -> uint32_t { return (uint32_t)wrap(p, nz) * pbytes; };
 
@@ -642,11 +646,12 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void stage_kernel(c
 // ---------------------------------------------------------------------------
 template <typename T>
 struct NoiseArgs {
-    T *out[9];
+    T *out[2][9];             // the two noise sets; step m writes set m & 1
     int nx, ny, nz, tz, gx, gy, gz;
     T dt_h, sd, st, so, s3;
     NoiseKey nk;              // step word taken from *step at run time
     const StepState *step;
+    uint32_t ahead;           // 0: noise of the step in flight, 1: of the next step
 };
 
 // Tile of the noise kernel: 32 x NTY<T> columns (32 in FP32, 16 in FP64,
@@ -665,7 +670,9 @@ __device__ __forceinline__ int nidx(int lx, int ly) { return (ly + 1) * NPX + (l
 template <typename T>
 __global__ __launch_bounds__(NOISE_THREADS<T>) void noise_kernel(const NoiseArgs<T> args) {
     NoiseArgs<T> a = args;
-    a.nk.step = args.step->cur;
+    const uint32_t m = args.step->cur + args.ahead;
+    a.nk.step = m;
+    T *const *out = (m & 1u) ? args.out[1] : args.out[0];
     __shared__ T s_S[2][5][NPX * (NTY<T> + 2)];  // [W_A, W_B][xx, yy, xy, xz, yz], current plane
     const int nx = a.nx, ny = a.ny, nz = a.nz, tz = a.tz;
     const int plane = nx * ny;
@@ -758,9 +765,9 @@ __global__ __launch_bounds__(NOISE_THREADS<T>) void noise_kernel(const NoiseArgs
             const int g = k * plane + own_xy;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                a.out[c][g] = N[0][c] - a.s3 * N[1][c];
-                a.out[3 + c][g] = N[0][c] + a.s3 * N[1][c];
-                a.out[6 + c][g] = N[0][c];
+                out[c][g] = N[0][c] - a.s3 * N[1][c];
+                out[3 + c][g] = N[0][c] + a.s3 * N[1][c];
+                out[6 + c][g] = N[0][c];
             }
         }
 #pragma unroll
@@ -1275,11 +1282,12 @@ struct SparseArgs {
     const T *drho;       // NOSLIP only
 };
 
-constexpr int SP_CAP = 128;   // candidates staged in LDS at a time
+constexpr int SP_CAP = 64;    // candidates staged in LDS at a time
+constexpr int SP_THREADS = 256;   // threads of a sparse block (one stage tile)
 constexpr int SP_BATCH = 4;   // items per thread whose loads are issued together
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(STAGE_THREADS) void k_sparse(const SparseArgs<T> a) {
+__global__ __launch_bounds__(SP_THREADS) void k_sparse(const SparseArgs<T> a) {
     __shared__ int32_t s_bc[SP_CAP][3], s_bf[SP_CAP][3], s_col[SP_CAP];
     __shared__ double s_wc[SP_CAP][9], s_wf[SP_CAP][9], s_v[SP_CAP][4];
     const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
@@ -1298,7 +1306,7 @@ __global__ __launch_bounds__(STAGE_THREADS) void k_sparse(const SparseArgs<T> a)
     for (int c0 = cb; c0 < ce; c0 += SP_CAP) {
         const int nc = min(SP_CAP, ce - c0);
         __syncthreads();
-        for (int i = tid; i < nc; i += STAGE_THREADS) {
+        for (int i = tid; i < nc; i += SP_THREADS) {
             const int pid = a.blk_list[c0 + i];
             s_col[i] = a.blk_color[c0 + i];
             for (int d = 0; d < 3; ++d) {
@@ -1323,14 +1331,14 @@ __global__ __launch_bounds__(STAGE_THREADS) void k_sparse(const SparseArgs<T> a)
             int r1 = r0 + 1;
             while (r1 < nc && s_col[r1] == col) ++r1;
             const int items = (r1 - r0) * per;
-            for (int base = 0; base < items; base += SP_BATCH * STAGE_THREADS) {
+            for (int base = 0; base < items; base += SP_BATCH * SP_THREADS) {
                 size_t gi[SP_BATCH];
                 double add[SP_BATCH];
                 int cmp[SP_BATCH];
                 bool ok[SP_BATCH];
 #pragma unroll
                 for (int bi = 0; bi < SP_BATCH; ++bi) {
-                    const int it = base + bi * STAGE_THREADS + tid;
+                    const int it = base + bi * SP_THREADS + tid;
                     ok[bi] = false;
                     gi[bi] = 0;
                     add[bi] = 0.0;
@@ -1440,85 +1448,87 @@ struct AdjArgs {
     double rho0, cf2, eta, lam_b, k, inv_h;   // lam_b = zeta - 2 eta / 3, k = dt / h
 };
 
-struct Cell {
-    int x, y, z, nx, ny, nz;
-    __device__ __forceinline__ size_t at(int a, int s) const {
-        int c[3] = {x, y, z};
-        const int n[3] = {nx, ny, nz};
-        c[a] += s;
-        if (c[a] < 0) c[a] += n[a];
-        if (c[a] >= n[a]) c[a] -= n[a];
-        return ((size_t)c[2] * ny + c[1]) * nx + c[0];
-    }
-    __device__ __forceinline__ size_t at2(int a, int s, int b, int t) const {
-        int c[3] = {x, y, z};
-        const int n[3] = {nx, ny, nz};
-        c[a] += s;
-        c[b] += t;
+// Wrapped coordinates of a cell and its neighbours at offsets -1..+2 along
+// each axis; flat index of the cell shifted by an offset vector.  The offset
+// vectors below are compile-time constants once the axis loops unroll.
+struct Nbr {
+    int X[4], Y[4], Z[4];   // coordinate + (k - 1), periodic
+    int nx, nxy;
+    __device__ __forceinline__ Nbr(int x, int y, int z, int nx_, int ny_, int nz_) : nx(nx_), nxy(nx_ * ny_) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            if (c[d] < 0) c[d] += n[d];
-            if (c[d] >= n[d]) c[d] -= n[d];
+        for (int k = 0; k < 4; ++k) {
+            int a = x + k - 1, b = y + k - 1, c = z + k - 1;
+            a += a < 0 ? nx_ : 0;
+            a -= a >= nx_ ? nx_ : 0;
+            b += b < 0 ? ny_ : 0;
+            b -= b >= ny_ ? ny_ : 0;
+            c += c < 0 ? nz_ : 0;
+            c -= c >= nz_ ? nz_ : 0;
+            X[k] = a;
+            Y[k] = b;
+            Z[k] = c * nxy;
         }
-        return ((size_t)c[2] * ny + c[1]) * nx + c[0];
+    }
+    // index of the cell shifted s along axis a and t along axis b
+    __device__ __forceinline__ int at(int a, int s, int b = 0, int t = 0) const {
+        int d[3] = {0, 0, 0};
+        d[a] += s;
+        d[b] += t;
+        return Z[d[2] + 1] + Y[d[1] + 1] * nx + X[d[0] + 1];
+    }
+    // same, shifted once more by +1 along axis c
+    __device__ __forceinline__ int at3(int a, int s, int b, int t, int c) const {
+        int d[3] = {0, 0, 0};
+        d[a] += s;
+        d[b] += t;
+        d[c] += 1;
+        return Z[d[2] + 1] + Y[d[1] + 1] * nx + X[d[0] + 1];
     }
 };
 
-template <typename T>
-struct AdjView {
-    const AdjArgs<T> &a;
-    __device__ double rf(int ax, size_t i, size_t ip) const {
-        return a.rho0 + 0.5 * ((double)a.U[0][i] + (double)a.U[0][ip]);
-    }
-    // v_ax at the cell whose flat index is i (its +ax neighbour is ip)
-    __device__ double v(int ax, size_t i, size_t ip) const {
-        return (double)a.U[1 + ax][i] / rf(ax, i, ip);
-    }
-    __device__ double g(int ax, size_t i) const { return (double)a.U[1 + ax][i]; }
-    __device__ double lg(int ax, size_t i) const { return (double)a.lam[1 + ax][i]; }
-};
+__device__ __forceinline__ void cell_of(int j, int nx, int ny, int &x, int &y, int &z) {
+    const int r = j / nx;
+    x = j - r * nx;
+    z = r / ny;
+    y = r - z * ny;
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_pass1(const AdjArgs<T> a) {
-    const size_t ncell = (size_t)a.nx * a.ny * a.nz;
-    const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncell = a.nx * a.ny * a.nz;
+    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (j >= ncell) return;
-    const Cell C{(int)(j % a.nx), (int)((j / a.nx) % a.ny), (int)(j / ((size_t)a.nx * a.ny)),
-                 a.nx, a.ny, a.nz};
-    const AdjView<T> W{a};
-    const double k = a.k, eta = a.eta, ih = a.inv_h;
-    // v_ax at cell C shifted by s along sa (and t along sb)
-    auto vat = [&](int ax, int sa, int s, int sb, int t) {
-        const size_t i = C.at2(sa, s, sb, t);
-        const Cell D{(int)(i % a.nx), (int)((i / a.nx) % a.ny), (int)(i / ((size_t)a.nx * a.ny)),
-                     a.nx, a.ny, a.nz};
-        return W.v(ax, i, D.at(ax, 1));
+    int x, y, z;
+    cell_of(j, a.nx, a.ny, x, y, z);
+    const Nbr N(x, y, z, a.nx, a.ny, a.nz);
+    const double k = a.k, eta = a.eta, ih = a.inv_h, rho0 = a.rho0;
+    const T *__restrict__ R = a.U[0];
+    // v_c = g_c / rho_face_c at the cell shifted (s along sa, t along sb)
+    auto vat = [&](int c, int sa, int s, int sb, int t) {
+        const double rf = rho0 + 0.5 * ((double)R[N.at(sa, s, sb, t)] + (double)R[N.at3(sa, s, sb, t, c)]);
+        return (double)a.U[1 + c][N.at(sa, s, sb, t)] / rf;
     };
-    auto gat = [&](int ax, int sa, int s, int sb, int t) { return W.g(ax, C.at2(sa, s, sb, t)); };
-    auto lgat = [&](int ax, int sa, int s, int sb, int t) { return W.lg(ax, C.at2(sa, s, sb, t)); };
-    // Every term below names its neighbour offsets explicitly; lgat(c, sa, s,
-    // sb, t) is lambda_g_c at the cell shifted s along sa and t along sb.
-    double mu_p = 0.0;
-    // mu_p at a shifted cell: sum over ax of -k (lg_ax[i - e_ax] - lg_ax[i])
+    auto gat = [&](int c, int sa, int s, int sb, int t) { return (double)a.U[1 + c][N.at(sa, s, sb, t)]; };
+    auto lgat = [&](int c, int sa, int s, int sb, int t) { return (double)a.lam[1 + c][N.at(sa, s, sb, t)]; };
+    // mu_p at the cell shifted s along sa: sum over c of -k (lg_c[i - e_c] - lg_c[i])
     auto mup_at = [&](int sa, int s) {
         double m = 0.0;
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax)
-            m += -k * (lgat(ax, sa, s, ax, -1) - lgat(ax, sa, s, ax, 0));
+        for (int c = 0; c < 3; ++c) m += -k * (lgat(c, sa, s, c, -1) - lgat(c, sa, s, c, 0));
         return m;
     };
-    mu_p = mup_at(0, 0);
-    double mug[3], muv[3];
+    const double mu_p = mup_at(0, 0);
+    double mug[3], murf[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         // mass: -k (lr[j] - lr[j+ax])
-        const double lr0 = (double)a.lam[0][j], lr1 = (double)a.lam[0][C.at(ax, 1)];
-        double mgv = -k * (lr0 - lr1);
+        double mgv = -k * ((double)a.lam[0][j] - (double)a.lam[0][N.at(ax, 1)]);
         double mvv = 0.0;
-        // centre flux C_ax at cells j and j+ax: muC_ax(i) = -k (lg_ax[i-ax] - lg_ax[i])
-        const double mC0 = -k * (lgat(ax, ax, -1, ax, 0) - lgat(ax, ax, 0, ax, 0));
-        const double mC1 = -k * (lgat(ax, ax, 0, ax, 0) - lgat(ax, ax, 1, ax, 0));
-        // B_ax(i) = v_ax(i) + v_ax(i-ax); A_ax(i) = (g_ax(i) + g_ax(i-ax)) / 4
+        // centre flux C_ax at cells j and j+ax: muC(i) = -k (lg_ax[i-ax] - lg_ax[i])
+        const double lgm = lgat(ax, ax, -1, ax, 0), lg0 = lgat(ax, ax, 0, ax, 0), lgp = lgat(ax, ax, 1, ax, 0);
+        const double mC0 = -k * (lgm - lg0);
+        const double mC1 = -k * (lg0 - lgp);
+        // B(i) = v_ax(i) + v_ax(i-ax); A(i) = (g_ax(i) + g_ax(i-ax)) / 4
         const double v0 = vat(ax, ax, 0, ax, 0), vm = vat(ax, ax, -1, ax, 0), vp = vat(ax, ax, 1, ax, 0);
         const double g0 = gat(ax, ax, 0, ax, 0), gm = gat(ax, ax, -1, ax, 0), gp = gat(ax, ax, 1, ax, 0);
         mgv += 0.25 * (v0 + vm) * mC0 + 0.25 * (vp + v0) * mC1;
@@ -1530,35 +1540,33 @@ __global__ __launch_bounds__(256) void k_adj_pass1(const AdjArgs<T> a) {
         for (int b = 0; b < 3; ++b) {
             if (b == ax) continue;
             // edge flux E_{ax b}(i) = (g_ax(i) + g_ax(i+b)) (v_b(i) + v_b(i+ax)) / 4 - visc;
-            // muE_{ax b}(i) = -k (lg_ax(i) - lg_ax(i+b)); it reaches g_ax at j from
-            // i = j and i = j - b
+            // muE(i) = -k (lg_ax(i) - lg_ax(i+b)) reaches g_ax at j from i = j and i = j - b
             const double mE0 = -k * (lgat(ax, b, 0, b, 0) - lgat(ax, b, 1, b, 0));
             const double mEm = -k * (lgat(ax, b, -1, b, 0) - lgat(ax, b, 0, b, 0));
             const double Q0 = vat(b, b, 0, ax, 0) + vat(b, ax, 1, b, 0);
             const double Qm = vat(b, b, -1, ax, 0) + vat(b, b, -1, ax, 1);
             mgv += 0.25 * Q0 * mE0 + 0.25 * Qm * mEm;
-            // viscous part of E_{ax b} as a function of v_ax: -eta/h (v_ax(i+b) - v_ax(i))
+            // viscous part of E_{ax b} in v_ax: -eta/h (v_ax(i+b) - v_ax(i))
             mvv += -eta * ih * (mEm - mE0);
-            // edge flux E_{b ax}(i) = (g_b(i) + g_b(i+ax)) (v_ax(i) + v_ax(i+b)) / 4 - visc,
-            // muE_{b ax}(i) = -k (lg_b(i) - lg_b(i+ax)); it reaches v_ax at j from
-            // i = j and i = j - b
+            // edge flux E_{b ax}(i) = (g_b(i) + g_b(i+ax)) (v_ax(i) + v_ax(i+b)) / 4 - visc;
+            // muF(i) = -k (lg_b(i) - lg_b(i+ax)) reaches v_ax at j from i = j and i = j - b
             const double mF0 = -k * (lgat(b, ax, 0, ax, 0) - lgat(b, ax, 1, ax, 0));
             const double mFm = -k * (lgat(b, b, -1, ax, 0) - lgat(b, b, -1, ax, 1));
             const double P0 = gat(b, ax, 0, ax, 0) + gat(b, ax, 1, ax, 0);
             const double Pm = gat(b, b, -1, ax, 0) + gat(b, b, -1, ax, 1);
             mvv += 0.25 * P0 * mF0 + 0.25 * Pm * mFm;
-            // viscous part of E_{b ax} as a function of v_ax: -eta/h (v_ax(i+b) - v_ax(i))
+            // viscous part of E_{b ax} in v_ax: -eta/h (v_ax(i+b) - v_ax(i))
             mvv += -eta * ih * (mFm - mF0);
         }
         // v_ax = g_ax / rf_ax
-        const double rfj = W.rf(ax, j, C.at(ax, 1));
+        const double rfj = rho0 + 0.5 * ((double)R[j] + (double)R[N.at(ax, 1)]);
         mug[ax] = mgv + mvv / rfj;
-        muv[ax] = -mvv * (g0 / rfj) / rfj;   // mu_rf
+        murf[ax] = -mvv * (g0 / rfj) / rfj;
     }
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         a.mu[ax][j] = (T)mug[ax];
-        a.mu[3 + ax][j] = (T)muv[ax];
+        a.mu[3 + ax][j] = (T)murf[ax];
     }
     a.mu[6][j] = (T)mu_p;
 }
@@ -1583,16 +1591,18 @@ struct AdjCombine {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_pass2(const AdjCombine<T> a) {
-    const size_t ncell = (size_t)a.nx * a.ny * a.nz;
-    const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncell = a.nx * a.ny * a.nz;
+    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (j >= ncell) return;
-    const Cell C{(int)(j % a.nx), (int)((j / a.nx) % a.ny), (int)(j / ((size_t)a.nx * a.ny)),
-                 a.nx, a.ny, a.nz};
+    int x, y, z;
+    cell_of(j, a.nx, a.ny, x, y, z);
+    const int jm[3] = {j + (x == 0 ? a.nx - 1 : -1), j + (y == 0 ? a.nx * (a.ny - 1) : -a.nx),
+                       j + (z == 0 ? a.nx * a.ny * (a.nz - 1) : -a.nx * a.ny)};
     double mu[4];
     mu[0] = a.cf2 * (double)a.mu[6][j];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-        mu[0] += 0.5 * ((double)a.mu[3 + ax][j] + (double)a.mu[3 + ax][C.at(ax, -1)]);
+        mu[0] += 0.5 * ((double)a.mu[3 + ax][j] + (double)a.mu[3 + ax][jm[ax]]);
         mu[1 + ax] = (double)a.mu[ax][j];
     }
 #pragma unroll
@@ -1721,12 +1731,12 @@ BinArgs bin_args(ic_ctx *c, int np, const double *qh) {
 inline unsigned wave_blocks(int n) { return (unsigned)((n * 64 + 255) / 256); }
 inline unsigned thread_blocks(int n) { return (unsigned)((n + 255) / 256); }
 
-void launch_binning(ic_ctx *c, int np, const double *qh) {
+void launch_binning(ic_ctx *c, int np, const double *qh, hipStream_t s) {
     const BinArgs b = bin_args(c, np, qh);
-    hipLaunchKernelGGL(k_bin_count, dim3(thread_blocks(np)), dim3(256), 0, c->stream, b);
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, c->stream, b);
-    hipLaunchKernelGGL(k_bin_fill, dim3(thread_blocks(np)), dim3(256), 0, c->stream, b);
-    hipLaunchKernelGGL(k_bin_sort, dim3(b.nblk), dim3(64), 0, c->stream, b);
+    hipLaunchKernelGGL(k_bin_count, dim3(thread_blocks(np)), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, b);
+    hipLaunchKernelGGL(k_bin_fill, dim3(thread_blocks(np)), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_bin_sort, dim3(b.nblk), dim3(64), 0, s, b);
 }
 
 template <typename T>
@@ -1744,8 +1754,14 @@ SparseArgs<T> sparse_args(ic_ctx *c) {
     return sa;
 }
 
+// One step on the context stream.  Beside it, on the side stream: the
+// particle prologue (half-step positions, kernel weights, stage-1 Omega,
+// binning), which only reads U^n and is joined before the first particle
+// stage term, and (FP32) the noise of the next step, which depends only on
+// the key and the step number, joined at the end of the step: the fluid
+// stages are memory-bound and the noise kernel ALU-bound.
 template <typename T>
-hipError_t step_impl(ic_ctx *c) {
+hipError_t step_impl(ic_ctx *c, bool overlap, bool first, bool last) {
     const ic_params &p = c->p;
     hipStream_t s = c->stream;
     const Workspace &w = c->ws;
@@ -1753,7 +1769,19 @@ hipError_t step_impl(ic_ctx *c) {
     const dim3 grid(c->nblk[0], c->nblk[1], c->nblk[2]);
     const unsigned nblk_all = (unsigned)(c->nblk[0] * c->nblk[1] * c->nblk[2]);
     const int np = c->np;
+    const bool noise = p.kT > 0.0;
+    // Next-step noise beside the stages in FP32 only: the FP64 noise kernel
+    // is FP64-ALU-bound for about 1.5 stage sweeps and, run concurrently,
+    // slowed the stage kernels by more than it hid (measured at 256^3).
+    if (!overlap || sizeof(T) == 8) first = last = true;
+    const bool ahead = noise && !last;
+    const bool side_part = overlap && np > 0;
+    const hipStream_t ps = side_part ? c->side : s;   // stream of the particle prologue
     PartArgs<T> pa = part_args<T>(c, U);
+    hipError_t err = hipSuccess;
+    auto chk = [&](hipError_t e) {
+        if (err == hipSuccess) err = e;
+    };
 
     {
         DriveArgs d{};
@@ -1766,9 +1794,14 @@ hipError_t step_impl(ic_ctx *c) {
         }
         hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(64), 0, s, w.st, d);
     }
+    if (side_part || ahead) {
+        chk(hipEventRecord(c->ev_fork, s));
+        chk(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+    }
     if (np > 0) {
-        hipLaunchKernelGGL(k_pre<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa);
-        launch_binning(c, np, w.qh);
+        hipLaunchKernelGGL(k_pre<T>, dim3(wave_blocks(np)), dim3(256), 0, ps, pa);
+        launch_binning(c, np, w.qh, ps);
+        if (side_part) chk(hipEventRecord(c->ev_part, c->side));
     }
 
     StageArgs<T> a{};
@@ -1782,11 +1815,12 @@ hipError_t step_impl(ic_ctx *c) {
     a.dt_h = (T)(p.dt / p.h);
     a.dt = (T)p.dt;
     a.fbytes = (uint32_t)((size_t)p.nx * p.ny * p.nz * sizeof(T));
+    a.st = w.st;
     const bool full = p.nx % TX == 0 && p.ny % TY == 0;
-    const bool noise = p.kT > 0.0;
     if (noise) {
         NoiseArgs<T> na{};
-        for (int i = 0; i < 9; ++i) na.out[i] = (T *)w.N[i];
+        for (int k = 0; k < 2; ++k)
+            for (int i = 0; i < 9; ++i) na.out[k][i] = (T *)w.N[k][i];
         na.nx = p.nx; na.ny = p.ny; na.nz = p.nz; na.tz = c->tz;
         na.gx = (p.nx + NTX - 1) / NTX; na.gy = (p.ny + NTY<T> - 1) / NTY<T>; na.gz = c->nblk[2];
         const double amp = 1.0 / sqrt(p.h * p.h * p.h * p.dt);
@@ -1799,8 +1833,16 @@ hipError_t step_impl(ic_ctx *c) {
         na.s3 = (T)sqrt(3.0);
         na.nk = NoiseKey{(uint32_t)(p.seed & 0xFFFFFFFFu), (uint32_t)(p.seed >> 32), 0u, p.replica};
         na.step = w.st;
-        hipLaunchKernelGGL(noise_kernel<T>, dim3(na.gx * na.gy * na.gz), dim3(NOISE_THREADS<T>), 0, s,
-                           na);
+        const dim3 ng(na.gx * na.gy * na.gz), nt(NOISE_THREADS<T>);
+        if (ahead) {
+            na.ahead = 1;
+            hipLaunchKernelGGL(noise_kernel<T>, ng, nt, 0, c->side, na);
+            chk(hipEventRecord(c->ev_noise, c->side));
+        }
+        if (first) {
+            na.ahead = 0;
+            hipLaunchKernelGGL(noise_kernel<T>, ng, nt, 0, s, na);
+        }
     }
     a.nmodes = c->forcing.nmodes;
     a.prof = w.prof;
@@ -1823,7 +1865,8 @@ hipError_t step_impl(ic_ctx *c) {
         }
         a.ra = (T)ra[st];
         a.rb = (T)rb[st];
-        for (int i = 0; i < 3; ++i) a.noise[i] = noise ? (const T *)w.N[3 * st + i] : nullptr;
+        for (int k = 0; k < 2; ++k)
+            for (int i = 0; i < 3; ++i) a.noise[k][i] = noise ? (const T *)w.N[k][3 * st + i] : nullptr;
         a.amp = w.st->amp[st];
         hipEvent_t e0 = prof_event(c), e1 = prof_event(c);
         if (e0) (void)hipEventRecord(e0, s);
@@ -1847,12 +1890,13 @@ hipError_t step_impl(ic_ctx *c) {
             prof_push(c, e0, e1);
         }
         if (np > 0) {
+            if (st == 0 && side_part) chk(hipStreamWaitEvent(s, c->ev_part, 0));
             SparseArgs<T> sa = sparse_args<T>(c);
             sa.b = rb[st];
             sa.val = w.F;
             sa.omega = w.omega;
             for (int i = 0; i < 3; ++i) sa.fields[i] = (T *)dst[st][1 + i];
-            hipLaunchKernelGGL((k_sparse<T, SP_STAGE>), grid, dim3(STAGE_THREADS), 0, s, sa);
+            hipLaunchKernelGGL((k_sparse<T, SP_STAGE>), grid, dim3(SP_THREADS), 0, s, sa);
         }
     }
 
@@ -1862,10 +1906,12 @@ hipError_t step_impl(ic_ctx *c) {
         sa.val = w.du;
         for (int i = 0; i < 3; ++i) sa.fields[i] = (T *)U[1 + i];
         sa.drho = (const T *)U[0];
-        hipLaunchKernelGGL((k_sparse<T, SP_NOSLIP>), grid, dim3(STAGE_THREADS), 0, s, sa);
+        hipLaunchKernelGGL((k_sparse<T, SP_NOSLIP>), grid, dim3(SP_THREADS), 0, s, sa);
         hipLaunchKernelGGL(k_final<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa);
     }
-    return hipGetLastError();
+    if (ahead) chk(hipStreamWaitEvent(s, c->ev_noise, 0));
+    chk(hipGetLastError());
+    return err;
 }
 
 template <typename T>
@@ -1885,13 +1931,13 @@ hipError_t spread_impl(ic_ctx *c, int n, const double *q, const double *f, int k
     const Grid G{p.nx, p.ny, p.nz, p.h, 1.0 / p.h, p.rho0};
     hipLaunchKernelGGL(k_weights, dim3(wave_blocks(n)), dim3(256), 0, c->stream, G, n, q, w.qh,
                        w.pk.bc, w.pk.bf, w.pk.wc, w.pk.wf);
-    launch_binning(c, n, w.qh);
+    launch_binning(c, n, w.qh, c->stream);
     SparseArgs<T> sa = sparse_args<T>(c);
     sa.val = f;
     sa.kind = kind;
     sa.fields[0] = (T *)field;
     const dim3 grid(c->nblk[0], c->nblk[1], c->nblk[2]);
-    hipLaunchKernelGGL((k_sparse<T, SP_SPREAD>), grid, dim3(STAGE_THREADS), 0, c->stream, sa);
+    hipLaunchKernelGGL((k_sparse<T, SP_SPREAD>), grid, dim3(SP_THREADS), 0, c->stream, sa);
     return hipGetLastError();
 }
 
@@ -2046,8 +2092,9 @@ hipError_t launch_adjoint_step(ic_ctx *c, int64_t n, const void *const Un[4], vo
                                 : adjoint_impl<float>(c, n, Un, lam);
 }
 
-hipError_t launch_step(ic_ctx *c) {
-    return c->p.prec == IC_FP64 ? step_impl<double>(c) : step_impl<float>(c);
+hipError_t launch_step(ic_ctx *c, bool overlap, bool first, bool last) {
+    return c->p.prec == IC_FP64 ? step_impl<double>(c, overlap, first, last)
+                                : step_impl<float>(c, overlap, first, last);
 }
 hipError_t launch_interpolate(ic_ctx *c, int n, const double *q, int kind, const void *field,
                               double *out) {

@@ -51,7 +51,10 @@ constexpr int TZ_MIN = 4;
 struct Workspace {
     void *A[4];          // stage buffer U~ (drho, gx, gy, gz)
     void *B[4];          // stage buffer U^{n+1/2}
-    void *N[9];          // stochastic increments of the three stages (x, y, z each); kT > 0 only
+    // stochastic increments of the three stages (x, y, z each), kT > 0 only;
+    // two sets: step n uses set n & 1, so the next step's set can be filled
+    // while this step runs
+    void *N[2][9];
     // persistent particle state, [N][3] or [N]
     double *q, *u, *me, *eps, *ks, *qeq, *fext;
     // per-step particle data
@@ -108,6 +111,10 @@ struct ic_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
     double prof_ms;
     int64_t prof_launches;
+    // side stream: particle prologue and next-step noise run beside the
+    // fluid stages (default priority); fork / join events
+    hipStream_t side;
+    hipEvent_t ev_fork, ev_part, ev_noise;
     // reverse mode (ic_bind_adjoint)
     bool adj_bound;
     ic::AdjWorkspace adj;
@@ -122,7 +129,12 @@ int nblocks_total(const ic_params &p);      // at the smallest z extent (workspa
 int nblocks_of(const ic_ctx *c);            // at the context's z extent
 
 // Launchers (ic_device.hip).  Each returns hipSuccess or the launch error.
-hipError_t launch_step(ic_ctx *c);
+// One IC step.  overlap: run the particle prologue and the next step's noise
+// on the side stream (eager stepping only, never under graph capture); then
+// first: the step's noise is not yet generated (first step of a call), last:
+// do not generate the next step's noise.  Without overlap every step runs on
+// the context stream and generates its own noise.
+hipError_t launch_step(ic_ctx *c, bool overlap, bool first, bool last);
 hipError_t launch_interpolate(ic_ctx *c, int n, const double *q, int kind, const void *field,
                               double *out);
 hipError_t launch_spread(ic_ctx *c, int n, const double *q, const double *f, int kind,
