@@ -1,14 +1,20 @@
-"""Parity at the full benchmark size: the paper-scale workload (256^3 cells,
-10^4 tethered particles of split contrast, kT = 1e-3, modal drive) advanced
-two steps in one ic_step call, in the launch configuration bench.py times
-(default stage tile, particle prologue on the side stream, and in FP32 the
-second step's noise generated beside the first step's stages), against two
-FP64 oracle steps over the whole grid, element by element.
+"""Parity at the full sizes of the three workloads, in the launch
+configuration bench.py times (default stage tile, particle prologue on the
+side stream, and in FP32 the next step's noise generated beside the current
+step's stages), against the FP64 oracle over the whole grid, element by
+element:
 
-Bars: FP64 e <= 1e-12; FP32 e <= 2e-5 after two steps from an
-FP32-representable state (the per-step FP32 bar of 1e-5, twice).  e is
-max|x_gpu - x_oracle| / max|x_oracle| per field and for u; q is compared as a
-periodic distance in units of h.  One oracle step takes ~15 s here.
+- paper scale: 256^3 cells, 10^4 tethered particles of split contrast,
+  kT = 1e-3, modal drive; two steps in one ic_step call (one oracle step
+  takes ~13 s);
+- thermal: 128^3 cells, 10^3 tethered particles, kT = 1e-3; FP64 checked
+  after steps 1 and 10;
+- standing wave: 32^3, kT = 0, the symmetric tethered pair under the
+  resonant drive; FP64 checked after 100 steps.
+
+Bars: FP64 e <= 1e-12; FP32 e <= 1e-5 per step from an FP32-representable
+state (2e-5 after two).  e is max|x_gpu - x_oracle| / max|x_oracle| per field
+and for u; q is compared as a periodic distance in units of h.
 """
 import time
 
@@ -37,6 +43,31 @@ def workload():
 def _rel(a, b):
     den = np.max(np.abs(b))
     return float(np.max(np.abs(a - b)) / (den if den > 0 else 1.0))
+
+
+def _sim(w, prec, drho, g):
+    from paper_1307_0702_amd import ic
+    from paper_1307_0702_amd.ic import Simulation
+    fl, p = w.fluid, w.particles
+    sim = Simulation(fl, prec=prec, max_particles=p.n)
+    sim.set_state(drho, g)
+    eps = np.array([ic.ic_eps_from_kappa_ratio(fl.cf, r) for r in p.kappa_ratio])
+    sim.set_particles(p.q, p.me, eps, ks=p.ks, qeq=p.qeq, fext=p.fext)
+    sim.set_forcing(modes_of(w))
+    return sim
+
+
+def _errs(sim, st, fl):
+    gd, gg = sim.get_state()
+    gq, gu = sim.get_particles()
+    errs = {"drho": _rel(gd, st["drho"]), "u": _rel(gu, st["u"])}
+    for a in range(3):
+        errs["g%d" % a] = _rel(gg[a], st["g"][a])
+    L = np.array([fl.nx, fl.ny, fl.nz]) * fl.h
+    dq = np.abs(gq - st["q"])
+    errs["q"] = float(np.max(np.minimum(dq, L - dq)) / fl.h)
+    print("  ", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    return errs
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
@@ -76,3 +107,39 @@ def test_paper_scale_two_steps_match_oracle(workload, prec, tol):
     print("  ", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     for k, v in errs.items():
         assert v <= tol, (k, v)
+
+
+@pytest.mark.parametrize("prec,tol,checks", [("fp64", 1e-12, (1, 10)), ("fp32", 1e-5, (1,))])
+def test_thermal_128_matches_oracle(prec, tol, checks):
+    w = W.thermal_128()
+    fl = w.fluid
+    drho, g = w.drho, w.g
+    if prec == "fp32":
+        drho = drho.astype(np.float32).astype(np.float64)
+        g = g.astype(np.float32).astype(np.float64)
+    print(f"thermal {fl.shape} particles {w.particles.n} {prec}", flush=True)
+    sim = _sim(w, prec, drho, g)
+    st = make_state(W.Workload(w.name, fl, w.particles, w.modes, drho, g, w.period_steps))
+    prm = fl.as_dict()
+    done = 0
+    for c in checks:
+        sim.step(c - done)
+        for _ in range(c - done):
+            st, _ = O.ic_step(st, prm, modes_of(w))
+        done = c
+        print(f"  after {c} steps", flush=True)
+        for k, v in _errs(sim, st, fl).items():
+            assert v <= tol, (c, k, v)
+
+
+def test_standing_wave_32_hundred_steps_match_oracle():
+    w = W.standing_wave_32()
+    fl = w.fluid
+    sim = _sim(w, "fp64", w.drho, w.g)
+    st = make_state(w)
+    prm = fl.as_dict()
+    sim.step(100)
+    for _ in range(100):
+        st, _ = O.ic_step(st, prm, modes_of(w))
+    for k, v in _errs(sim, st, fl).items():
+        assert v <= 1e-12, (k, v)
