@@ -213,8 +213,8 @@ int ic_graph_destroy(ic_graph *graph);
  * earlier state and to the drive amplitudes A_m (Sec. VI pressure drive).
  * The step is the three SSP-RK3 stages of App. A with the conservative
  * staggered flux; its transpose runs the stages backwards.
- * ic_adjoint_workspace_size: bytes of the extra device workspace (19 fields
- * of the context precision plus IC_MAX_MODES x 1024 doubles).
+ * ic_adjoint_workspace_size: bytes of the extra device workspace (16 fields
+ * of the context precision plus IC_MAX_MODES doubles per 256 cells).
  * ic_bind_adjoint: binds it (caller-owned, 256-byte aligned) and zeroes the
  * drive-gradient accumulator.  Synchronising.
  * ic_adjoint_step: for step n taken from the state U^n = (drho, gx, gy, gz)

@@ -102,8 +102,9 @@ static size_t adj_layout(const ic_params &p, char *base, AdjWorkspace *aw) {
     for (int i = 0; i < 4; ++i) w.L2[i] = take(ncell * esz);
     for (int i = 0; i < 4; ++i) w.L1[i] = take(ncell * esz);
     for (int i = 0; i < 4; ++i) w.acc[i] = take(ncell * esz);
-    for (int i = 0; i < 7; ++i) w.mu[i] = take(ncell * esz);
-    w.partial = (double *)take((size_t)IC_MAX_MODES * ADJ_BLOCKS * sizeof(double));
+    for (int i = 0; i < 3; ++i) w.murf[i] = take(ncell * esz);
+    w.mur = take(ncell * esz);
+    w.partial = (double *)take((size_t)IC_MAX_MODES * adjoint_blocks(p) * sizeof(double));
     if (aw) *aw = w;
     return off;
 }
@@ -602,8 +603,8 @@ int ic_bind_adjoint(ic_ctx *c, void *workspace, size_t bytes) {
     if (((uintptr_t)workspace & 255) != 0) return fail(c, IC_E_ARG, "adjoint workspace not 256-byte aligned");
     if (bytes < adjoint_workspace_bytes(c->p)) return fail(c, IC_E_ARG, "adjoint workspace too small");
     carve_adjoint(c->p, (char *)workspace, c->adj);
-    hipError_t e = hipMemsetAsync(c->adj.partial, 0, (size_t)IC_MAX_MODES * ADJ_BLOCKS * sizeof(double),
-                                  c->stream);
+    hipError_t e = hipMemsetAsync(c->adj.partial, 0,
+                                  (size_t)IC_MAX_MODES * adjoint_blocks(c->p) * sizeof(double), c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "bind adjoint");
     c->adj_bound = true;
@@ -630,14 +631,15 @@ int ic_adjoint_step(ic_ctx *c, int64_t n, const void *drho, const void *gx, cons
 int ic_adjoint_drive(ic_ctx *c, double *grad, int32_t reset) {
     if (!c || !grad) return IC_E_ARG;
     if (!c->adj_bound) return fail(c, IC_E_STATE, "adjoint workspace not bound");
-    std::vector<double> part((size_t)IC_MAX_MODES * ADJ_BLOCKS);
+    const int nb = adjoint_blocks(c->p);
+    std::vector<double> part((size_t)IC_MAX_MODES * nb);
     hipError_t e = hipMemcpyAsync(part.data(), c->adj.partial, part.size() * sizeof(double),
                                   hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint drive read");
     for (int m = 0; m < c->forcing.nmodes; ++m) {
         double sum = 0.0;
-        for (int b = 0; b < ADJ_BLOCKS; ++b) sum += part[(size_t)m * ADJ_BLOCKS + b];
+        for (int b = 0; b < nb; ++b) sum += part[(size_t)m * nb + b];
         grad[m] = sum;
     }
     if (reset) {

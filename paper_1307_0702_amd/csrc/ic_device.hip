@@ -1433,20 +1433,56 @@ __global__ __launch_bounds__(SP_THREADS) void k_sparse(const SparseArgs<T> a) {
 // Adjoint (reverse mode) of one deterministic, particle-free RK3 step: the
 // transpose of the stage increment Delta(U) (conservative staggered flux of
 // the stage kernel, App. A) applied to an adjoint state lambda, one cell per
-// thread, neighbours read through the caches.
-//   pass 1: mu_g (incl. the v = g / rho_face chain), mu_rf = d/d rho_face,
-//           mu_p = sum of the centre-flux adjoints (drive gradient)
-//   pass 2: mu_rho = c_f^2 mu_p + (mu_rf[i] + mu_rf[i-a]) / 2, and the RK
-//           combination out = cs (lambda + mu), acc += ds lambda
+// thread, neighbours read through the caches, arithmetic in the context
+// precision.
+//   k_adj_mom: the momentum part mu_g (incl. the v = g / rho_face chain), the
+//     face-density adjoints mu_rf = d/d rho_face and mu_p (sum of the
+//     centre-flux adjoints); writes the momentum components of the RK
+//     combination, mu_rf and mu_rpart = c_f^2 mu_p + (sum_a mu_rf_a) / 2,
+//     and per-block partial sums of mu_p prof_m (drive-amplitude gradient).
+//   k_adj_rho: mu_rho = mu_rpart + (sum_a mu_rf_a[i - e_a]) / 2 and the
+//     density component of the RK combination.
+// RK combination of the reversed stages (U^{n+1} = U^n/3 + 2/3 (U2 + D(U2)),
+// U2 = 3/4 U^n + 1/4 (U1 + D(U1)), U1 = U^n + D(U^n)):
+//   ADJ_FIRST (stage 3): out = cs (lam + mu), acc  = ds lam
+//   ADJ_MID   (stage 2): out = cs (lam + mu), acc += ds lam
+//   ADJ_LAST  (stage 1): out = acc + cs (lam + mu)
 // ---------------------------------------------------------------------------
+enum AdjMode { ADJ_FIRST = 0, ADJ_MID = 1, ADJ_LAST = 2 };
+
+struct DriveCoef {
+    int axis[IC_MAX_MODES];
+    double c[IC_MAX_MODES];   // weight of the stage times sin(omega t_s + phase)
+};
+
 template <typename T>
 struct AdjArgs {
     const T *U[4];      // stage input (drho, gx, gy, gz)
     const T *lam[4];    // adjoint of the stage output
-    T *mu[7];           // mu_gx, mu_gy, mu_gz, mu_rf x3, mu_p
+    T *out[4];          // adjoint of the stage input (RK-combined)
+    T *acc[4];          // dL/dU^n accumulator
+    T *murf[3];         // mu_rf per axis
+    T *mur;             // c_f^2 mu_p + (sum_a mu_rf_a) / 2
     int nx, ny, nz;
-    double rho0, cf2, eta, lam_b, k, inv_h;   // lam_b = zeta - 2 eta / 3, k = dt / h
+    int mode;
+    double rho0, cf2, eta, lam_b, k, inv_h, cs, ds;   // lam_b = zeta - 2 eta / 3, k = dt / h
+    int nmodes, pstride;
+    DriveCoef dc;
+    const double *prof;
+    double *partial;    // [IC_MAX_MODES][gridDim.x]
 };
+
+template <typename T>
+__device__ __forceinline__ void adj_combine(const AdjArgs<T> &a, int c, int j, T l, T mu) {
+    const T o = (T)a.cs * (l + mu);
+    if (a.mode == ADJ_LAST) {
+        a.out[c][j] = a.acc[c][j] + o;
+    } else {
+        a.out[c][j] = o;
+        const T prev = a.mode == ADJ_MID ? a.acc[c][j] : (T)0;
+        a.acc[c][j] = prev + (T)a.ds * l;
+    }
+}
 
 // Wrapped coordinates of a cell and its neighbours at offsets -1..+2 along
 // each axis; flat index of the cell shifted by an offset vector.  The offset
@@ -1494,103 +1530,107 @@ __device__ __forceinline__ void cell_of(int j, int nx, int ny, int &x, int &y, i
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_adj_pass1(const AdjArgs<T> a) {
+__global__ __launch_bounds__(256) void k_adj_mom(const AdjArgs<T> a) {
+    using C = T;
     const int ncell = a.nx * a.ny * a.nz;
     const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (j >= ncell) return;
-    int x, y, z;
-    cell_of(j, a.nx, a.ny, x, y, z);
-    const Nbr N(x, y, z, a.nx, a.ny, a.nz);
-    const double k = a.k, eta = a.eta, ih = a.inv_h, rho0 = a.rho0;
-    const T *__restrict__ R = a.U[0];
-    // v_c = g_c / rho_face_c at the cell shifted (s along sa, t along sb)
-    auto vat = [&](int c, int sa, int s, int sb, int t) {
-        const double rf = rho0 + 0.5 * ((double)R[N.at(sa, s, sb, t)] + (double)R[N.at3(sa, s, sb, t, c)]);
-        return (double)a.U[1 + c][N.at(sa, s, sb, t)] / rf;
-    };
-    auto gat = [&](int c, int sa, int s, int sb, int t) { return (double)a.U[1 + c][N.at(sa, s, sb, t)]; };
-    auto lgat = [&](int c, int sa, int s, int sb, int t) { return (double)a.lam[1 + c][N.at(sa, s, sb, t)]; };
-    // mu_p at the cell shifted s along sa: sum over c of -k (lg_c[i - e_c] - lg_c[i])
-    auto mup_at = [&](int sa, int s) {
-        double m = 0.0;
+    const bool live = j < ncell;
+    int x = 0, y = 0, z = 0;
+    C mu_p = 0;
+    if (live) {
+        cell_of(j, a.nx, a.ny, x, y, z);
+        const Nbr N(x, y, z, a.nx, a.ny, a.nz);
+        const C k = (C)a.k, eta = (C)a.eta, ih = (C)a.inv_h, rho0 = (C)a.rho0, half = (C)0.5,
+                quarter = (C)0.25, lam_b = (C)a.lam_b;
+        const T *__restrict__ R = a.U[0];
+        // v_c = g_c / rho_face_c at the cell shifted (s along sa, t along sb)
+        auto vat = [&](int c, int sa, int s, int sb, int t) {
+            const C rf = rho0 + half * (R[N.at(sa, s, sb, t)] + R[N.at3(sa, s, sb, t, c)]);
+            return a.U[1 + c][N.at(sa, s, sb, t)] / rf;
+        };
+        auto gat = [&](int c, int sa, int s, int sb, int t) { return (C)a.U[1 + c][N.at(sa, s, sb, t)]; };
+        auto lgat = [&](int c, int sa, int s, int sb, int t) { return (C)a.lam[1 + c][N.at(sa, s, sb, t)]; };
+        // mu_p at the cell shifted s along sa: sum over c of -k (lg_c[i - e_c] - lg_c[i])
+        auto mup_at = [&](int sa, int s) {
+            C m = 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) m += -k * (lgat(c, sa, s, c, -1) - lgat(c, sa, s, c, 0));
-        return m;
-    };
-    const double mu_p = mup_at(0, 0);
-    double mug[3], murf[3];
+            for (int c = 0; c < 3; ++c) m += -k * (lgat(c, sa, s, c, -1) - lgat(c, sa, s, c, 0));
+            return m;
+        };
+        mu_p = mup_at(0, 0);
+        C murf[3];
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        // mass: -k (lr[j] - lr[j+ax])
-        double mgv = -k * ((double)a.lam[0][j] - (double)a.lam[0][N.at(ax, 1)]);
-        double mvv = 0.0;
-        // centre flux C_ax at cells j and j+ax: muC(i) = -k (lg_ax[i-ax] - lg_ax[i])
-        const double lgm = lgat(ax, ax, -1, ax, 0), lg0 = lgat(ax, ax, 0, ax, 0), lgp = lgat(ax, ax, 1, ax, 0);
-        const double mC0 = -k * (lgm - lg0);
-        const double mC1 = -k * (lg0 - lgp);
-        // B(i) = v_ax(i) + v_ax(i-ax); A(i) = (g_ax(i) + g_ax(i-ax)) / 4
-        const double v0 = vat(ax, ax, 0, ax, 0), vm = vat(ax, ax, -1, ax, 0), vp = vat(ax, ax, 1, ax, 0);
-        const double g0 = gat(ax, ax, 0, ax, 0), gm = gat(ax, ax, -1, ax, 0), gp = gat(ax, ax, 1, ax, 0);
-        mgv += 0.25 * (v0 + vm) * mC0 + 0.25 * (vp + v0) * mC1;
-        mvv += 0.25 * (g0 + gm) * mC0 + 0.25 * (gp + g0) * mC1;
-        mvv += -2.0 * eta * ih * (mC0 - mC1);
-        // bulk: mu_div(i) = -lam_b mu_p(i); mu_v_ax += (mu_div(j) - mu_div(j+ax)) / h
-        mvv += -a.lam_b * (mu_p - mup_at(ax, 1)) * ih;
+        for (int ax = 0; ax < 3; ++ax) {
+            // mass: -k (lr[j] - lr[j+ax])
+            C mgv = -k * ((C)a.lam[0][j] - (C)a.lam[0][N.at(ax, 1)]);
+            C mvv = 0;
+            // centre flux C_ax at cells j and j+ax: muC(i) = -k (lg_ax[i-ax] - lg_ax[i])
+            const C lgm = lgat(ax, ax, -1, ax, 0), lg0 = lgat(ax, ax, 0, ax, 0), lgp = lgat(ax, ax, 1, ax, 0);
+            const C mC0 = -k * (lgm - lg0);
+            const C mC1 = -k * (lg0 - lgp);
+            // B(i) = v_ax(i) + v_ax(i-ax); A(i) = (g_ax(i) + g_ax(i-ax)) / 4
+            const C v0 = vat(ax, ax, 0, ax, 0), vm = vat(ax, ax, -1, ax, 0), vp = vat(ax, ax, 1, ax, 0);
+            const C g0 = gat(ax, ax, 0, ax, 0), gm = gat(ax, ax, -1, ax, 0), gp = gat(ax, ax, 1, ax, 0);
+            mgv += quarter * (v0 + vm) * mC0 + quarter * (vp + v0) * mC1;
+            mvv += quarter * (g0 + gm) * mC0 + quarter * (gp + g0) * mC1;
+            mvv += -2 * eta * ih * (mC0 - mC1);
+            // bulk: mu_div(i) = -lam_b mu_p(i); mu_v_ax += (mu_div(j) - mu_div(j+ax)) / h
+            mvv += -lam_b * (mu_p - mup_at(ax, 1)) * ih;
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            if (b == ax) continue;
-            // edge flux E_{ax b}(i) = (g_ax(i) + g_ax(i+b)) (v_b(i) + v_b(i+ax)) / 4 - visc;
-            // muE(i) = -k (lg_ax(i) - lg_ax(i+b)) reaches g_ax at j from i = j and i = j - b
-            const double mE0 = -k * (lgat(ax, b, 0, b, 0) - lgat(ax, b, 1, b, 0));
-            const double mEm = -k * (lgat(ax, b, -1, b, 0) - lgat(ax, b, 0, b, 0));
-            const double Q0 = vat(b, b, 0, ax, 0) + vat(b, ax, 1, b, 0);
-            const double Qm = vat(b, b, -1, ax, 0) + vat(b, b, -1, ax, 1);
-            mgv += 0.25 * Q0 * mE0 + 0.25 * Qm * mEm;
-            // viscous part of E_{ax b} in v_ax: -eta/h (v_ax(i+b) - v_ax(i))
-            mvv += -eta * ih * (mEm - mE0);
-            // edge flux E_{b ax}(i) = (g_b(i) + g_b(i+ax)) (v_ax(i) + v_ax(i+b)) / 4 - visc;
-            // muF(i) = -k (lg_b(i) - lg_b(i+ax)) reaches v_ax at j from i = j and i = j - b
-            const double mF0 = -k * (lgat(b, ax, 0, ax, 0) - lgat(b, ax, 1, ax, 0));
-            const double mFm = -k * (lgat(b, b, -1, ax, 0) - lgat(b, b, -1, ax, 1));
-            const double P0 = gat(b, ax, 0, ax, 0) + gat(b, ax, 1, ax, 0);
-            const double Pm = gat(b, b, -1, ax, 0) + gat(b, b, -1, ax, 1);
-            mvv += 0.25 * P0 * mF0 + 0.25 * Pm * mFm;
-            // viscous part of E_{b ax} in v_ax: -eta/h (v_ax(i+b) - v_ax(i))
-            mvv += -eta * ih * (mFm - mF0);
+            for (int b = 0; b < 3; ++b) {
+                if (b == ax) continue;
+                // edge flux E_{ax b}(i) = (g_ax(i) + g_ax(i+b)) (v_b(i) + v_b(i+ax)) / 4 - visc;
+                // muE(i) = -k (lg_ax(i) - lg_ax(i+b)) reaches g_ax at j from i = j and i = j - b
+                const C mE0 = -k * (lgat(ax, b, 0, b, 0) - lgat(ax, b, 1, b, 0));
+                const C mEm = -k * (lgat(ax, b, -1, b, 0) - lgat(ax, b, 0, b, 0));
+                const C Q0 = vat(b, b, 0, ax, 0) + vat(b, ax, 1, b, 0);
+                const C Qm = vat(b, b, -1, ax, 0) + vat(b, b, -1, ax, 1);
+                mgv += quarter * Q0 * mE0 + quarter * Qm * mEm;
+                // viscous part of E_{ax b} in v_ax: -eta/h (v_ax(i+b) - v_ax(i))
+                mvv += -eta * ih * (mEm - mE0);
+                // edge flux E_{b ax}(i) = (g_b(i) + g_b(i+ax)) (v_ax(i) + v_ax(i+b)) / 4 - visc;
+                // muF(i) = -k (lg_b(i) - lg_b(i+ax)) reaches v_ax at j from i = j and i = j - b
+                const C mF0 = -k * (lgat(b, ax, 0, ax, 0) - lgat(b, ax, 1, ax, 0));
+                const C mFm = -k * (lgat(b, b, -1, ax, 0) - lgat(b, b, -1, ax, 1));
+                const C P0 = gat(b, ax, 0, ax, 0) + gat(b, ax, 1, ax, 0);
+                const C Pm = gat(b, b, -1, ax, 0) + gat(b, b, -1, ax, 1);
+                mvv += quarter * P0 * mF0 + quarter * Pm * mFm;
+                // viscous part of E_{b ax} in v_ax: -eta/h (v_ax(i+b) - v_ax(i))
+                mvv += -eta * ih * (mFm - mF0);
+            }
+            // v_ax = g_ax / rf_ax
+            const C irf = (C)1 / (rho0 + half * (R[j] + R[N.at(ax, 1)]));
+            adj_combine(a, 1 + ax, j, lg0, mgv + mvv * irf);
+            murf[ax] = -mvv * (g0 * irf) * irf;
         }
-        // v_ax = g_ax / rf_ax
-        const double rfj = rho0 + 0.5 * ((double)R[j] + (double)R[N.at(ax, 1)]);
-        mug[ax] = mgv + mvv / rfj;
-        murf[ax] = -mvv * (g0 / rfj) / rfj;
-    }
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        a.mu[ax][j] = (T)mug[ax];
-        a.mu[3 + ax][j] = (T)murf[ax];
+        for (int ax = 0; ax < 3; ++ax) a.murf[ax][j] = murf[ax];
+        a.mur[j] = (C)a.cf2 * mu_p + half * (murf[0] + murf[1] + murf[2]);
     }
-    a.mu[6][j] = (T)mu_p;
+    if (a.nmodes > 0) {
+        // per-block partials of coef_m sum_j mu_p(j) prof_m(j), fixed order
+        __shared__ double s_red[IC_MAX_MODES][4];
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+        for (int m = 0; m < IC_MAX_MODES; ++m) {
+            if (m >= a.nmodes) break;
+            const int ax = a.dc.axis[m];
+            double v = live ? (double)mu_p * a.prof[m * a.pstride + (ax == 0 ? x : (ax == 1 ? y : z))] : 0.0;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) s_red[m][wave] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < (unsigned)a.nmodes) {
+            const int m = threadIdx.x;
+            const double sum = ((s_red[m][0] + s_red[m][1]) + s_red[m][2]) + s_red[m][3];
+            a.partial[m * gridDim.x + blockIdx.x] += a.dc.c[m] * sum;
+        }
+    }
 }
 
-// RK combination of the reversed stages (U^{n+1} = U^n/3 + 2/3 (U2 + D(U2)),
-// U2 = 3/4 U^n + 1/4 (U1 + D(U1)), U1 = U^n + D(U^n)):
-//   ADJ_FIRST (stage 3): out = cs (lam + mu), acc  = ds lam
-//   ADJ_MID   (stage 2): out = cs (lam + mu), acc += ds lam
-//   ADJ_LAST  (stage 1): out = acc + cs (lam + mu)
-enum AdjMode { ADJ_FIRST = 0, ADJ_MID = 1, ADJ_LAST = 2 };
-
 template <typename T>
-struct AdjCombine {
-    const T *lam[4];
-    const T *mu[7];
-    T *out[4];
-    T *acc[4];
-    int nx, ny, nz;
-    double cf2, cs, ds;
-    int mode;
-};
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_adj_pass2(const AdjCombine<T> a) {
+__global__ __launch_bounds__(256) void k_adj_rho(const AdjArgs<T> a) {
     const int ncell = a.nx * a.ny * a.nz;
     const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (j >= ncell) return;
@@ -1598,64 +1638,8 @@ __global__ __launch_bounds__(256) void k_adj_pass2(const AdjCombine<T> a) {
     cell_of(j, a.nx, a.ny, x, y, z);
     const int jm[3] = {j + (x == 0 ? a.nx - 1 : -1), j + (y == 0 ? a.nx * (a.ny - 1) : -a.nx),
                        j + (z == 0 ? a.nx * a.ny * (a.nz - 1) : -a.nx * a.ny)};
-    double mu[4];
-    mu[0] = a.cf2 * (double)a.mu[6][j];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        mu[0] += 0.5 * ((double)a.mu[3 + ax][j] + (double)a.mu[3 + ax][jm[ax]]);
-        mu[1 + ax] = (double)a.mu[ax][j];
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const double l = (double)a.lam[c][j];
-        const double o = a.cs * (l + mu[c]);
-        if (a.mode == ADJ_LAST) {
-            a.out[c][j] = (T)((double)a.acc[c][j] + o);
-        } else {
-            a.out[c][j] = (T)o;
-            const double prev = a.mode == ADJ_MID ? (double)a.acc[c][j] : 0.0;
-            a.acc[c][j] = (T)(prev + a.ds * l);
-        }
-    }
-}
-
-struct DriveCoef {
-    int axis[IC_MAX_MODES];
-    double c[IC_MAX_MODES];
-};
-
-// partial[m][block] += coef[m] * sum over the block's cells of mu_p prof_m
-// (fixed block order: the host adds the partials in order)
-template <typename T>
-__global__ __launch_bounds__(256) void k_adj_drive(const T *mu_p, int nx, int ny, int nz, int nmodes,
-                                                   const double *prof, int pstride, DriveCoef coef,
-                                                   double *partial) {
-    __shared__ double s[IC_MAX_MODES][256];
-    const size_t n = (size_t)nx * ny * nz;
-    double acc[IC_MAX_MODES];
-#pragma unroll
-    for (int m = 0; m < IC_MAX_MODES; ++m) acc[m] = 0.0;
-    for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
-         j += (size_t)gridDim.x * blockDim.x) {
-        const int x = (int)(j % nx), y = (int)((j / nx) % ny), z = (int)(j / ((size_t)nx * ny));
-        const double mp = (double)mu_p[j];
-#pragma unroll
-        for (int m = 0; m < IC_MAX_MODES; ++m) {
-            if (m >= nmodes) break;
-            const int ax = coef.axis[m];
-            acc[m] += mp * prof[m * pstride + (ax == 0 ? x : (ax == 1 ? y : z))];
-        }
-    }
-#pragma unroll
-    for (int m = 0; m < IC_MAX_MODES; ++m) s[m][threadIdx.x] = acc[m];
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o)
-            for (int m = 0; m < nmodes; ++m) s[m][threadIdx.x] += s[m][threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int m = 0; m < nmodes; ++m) partial[m * gridDim.x + blockIdx.x] += coef.c[m] * s[m][0];
+    const T mu = a.mur[j] + (T)0.5 * ((a.murf[0][jm[0]] + a.murf[1][jm[1]]) + a.murf[2][jm[2]]);
+    adj_combine(a, 0, j, a.lam[0][j], mu);
 }
 
 // FP64 block partial sums of the four fields (deterministic order).
@@ -1971,7 +1955,7 @@ hipError_t sums_impl(ic_ctx *c, double *host4) {
 
 }  // namespace
 
-// Reverse of one deterministic particle-free step (see k_adj_pass1).  The
+// Reverse of one deterministic particle-free step (see k_adj_mom).  The
 // stage inputs U1, U2 of step n are recomputed from U^n with the forward
 // stage kernels into the workspace stage buffers.
 template <typename T>
@@ -2048,40 +2032,32 @@ hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *con
         for (int i = 0; i < 4; ++i) {
             x.U[i] = (const T *)Uin[st][i];
             x.lam[i] = (const T *)Lin[st][i];
+            x.out[i] = (T *)Lout[st][i];
+            x.acc[i] = (T *)aw.acc[i];
         }
-        for (int i = 0; i < 7; ++i) x.mu[i] = (T *)aw.mu[i];
+        for (int i = 0; i < 3; ++i) x.murf[i] = (T *)aw.murf[i];
+        x.mur = (T *)aw.mur;
         x.nx = p.nx; x.ny = p.ny; x.nz = p.nz;
+        x.mode = st == 2 ? ADJ_FIRST : (st == 1 ? ADJ_MID : ADJ_LAST);
         x.rho0 = p.rho0;
         x.cf2 = p.cf * p.cf;
         x.eta = p.eta;
         x.lam_b = p.zeta - 2.0 * p.eta / 3.0;
         x.k = p.dt / p.h;
         x.inv_h = 1.0 / p.h;
-        hipLaunchKernelGGL(k_adj_pass1<T>, dim3(nb), dim3(256), 0, s, x);
-        if (c->forcing.nmodes > 0) {
-            DriveCoef dc{};
-            for (int m = 0; m < c->forcing.nmodes; ++m) {
-                const ic_mode &md = c->forcing.modes[m];
-                dc.axis[m] = md.axis;
-                dc.c[m] = cs[st] * sin(md.omega * ts[st] + md.phase);
-            }
-            hipLaunchKernelGGL(k_adj_drive<T>, dim3(ADJ_BLOCKS), dim3(256), 0, s, (const T *)aw.mu[6],
-                               p.nx, p.ny, p.nz, c->forcing.nmodes, (const double *)w.prof,
-                               c->prof_stride, dc, aw.partial);
+        x.cs = cs[st];
+        x.ds = ds[st];
+        x.nmodes = c->forcing.nmodes;
+        x.pstride = c->prof_stride;
+        x.prof = w.prof;
+        x.partial = aw.partial;
+        for (int m = 0; m < c->forcing.nmodes; ++m) {
+            const ic_mode &md = c->forcing.modes[m];
+            x.dc.axis[m] = md.axis;
+            x.dc.c[m] = cs[st] * sin(md.omega * ts[st] + md.phase);
         }
-        AdjCombine<T> cmb{};
-        for (int i = 0; i < 4; ++i) {
-            cmb.lam[i] = (const T *)Lin[st][i];
-            cmb.out[i] = (T *)Lout[st][i];
-            cmb.acc[i] = (T *)aw.acc[i];
-        }
-        for (int i = 0; i < 7; ++i) cmb.mu[i] = (const T *)aw.mu[i];
-        cmb.nx = p.nx; cmb.ny = p.ny; cmb.nz = p.nz;
-        cmb.cf2 = p.cf * p.cf;
-        cmb.cs = cs[st];
-        cmb.ds = ds[st];
-        cmb.mode = st == 2 ? ADJ_FIRST : (st == 1 ? ADJ_MID : ADJ_LAST);
-        hipLaunchKernelGGL(k_adj_pass2<T>, dim3(nb), dim3(256), 0, s, cmb);
+        hipLaunchKernelGGL(k_adj_mom<T>, dim3(nb), dim3(256), 0, s, x);
+        hipLaunchKernelGGL(k_adj_rho<T>, dim3(nb), dim3(256), 0, s, x);
     }
     hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, w.st, (int64_t)c->step);
     return hipGetLastError();

@@ -73,13 +73,13 @@ struct Workspace {
 };
 
 // Adjoint workspace (ic_bind_adjoint): adjoint stage states, the
-// accumulator of dL/dU^n, the transposed-increment fields and the per-block
-// partial sums of the drive-amplitude gradient.
-constexpr int ADJ_BLOCKS = 1024;
+// accumulator of dL/dU^n, the face-density adjoints and the per-block
+// partial sums of the drive-amplitude gradient (one block per 256 cells).
 struct AdjWorkspace {
-    void *L2[4], *L1[4], *acc[4], *mu[7];
-    double *partial;   // [IC_MAX_MODES][ADJ_BLOCKS]
+    void *L2[4], *L1[4], *acc[4], *murf[3], *mur;
+    double *partial;   // [IC_MAX_MODES][adjoint_blocks]
 };
+inline int adjoint_blocks(const ic_params &p) { return (int)(((size_t)p.nx * p.ny * p.nz + 255) / 256); }
 size_t adjoint_workspace_bytes(const ic_params &p);
 void carve_adjoint(const ic_params &p, char *base, AdjWorkspace &aw);
 
