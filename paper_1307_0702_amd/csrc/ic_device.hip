@@ -1469,7 +1469,9 @@ struct AdjArgs {
     int nmodes, pstride;
     DriveCoef dc;
     const double *prof;
-    double *partial;    // [IC_MAX_MODES][gridDim.x]
+    double *partial;    // [IC_MAX_MODES][nbp], one slot per block
+    int nbp;
+    int tz, gx, gy, gz; // tiled momentum pass: z extent and tile counts
 };
 
 template <typename T>
@@ -1624,7 +1626,231 @@ __global__ __launch_bounds__(256) void k_adj_mom(const AdjArgs<T> a) {
         if (threadIdx.x < (unsigned)a.nmodes) {
             const int m = threadIdx.x;
             const double sum = ((s_red[m][0] + s_red[m][1]) + s_red[m][2]) + s_red[m][3];
-            a.partial[m * gridDim.x + blockIdx.x] += a.dc.c[m] * sum;
+            a.partial[m * a.nbp + blockIdx.x] += a.dc.c[m] * sum;
+        }
+    }
+}
+
+// Tiled momentum pass (same arithmetic as k_adj_mom): a tile of ATX x ATY
+// columns marches over tz planes in z.  LDS holds three planes (k-1, k, k+1)
+// of lambda_g, g, v = g / rho_face and lambda_rho, and three density planes
+// (k, k+1, k+2), each with a one-cell halo (two on the high side for
+// density), so a cell's neighbour reads come from LDS and each velocity is
+// divided out once per point.  Per plane k: commit the prefetched plane k+1
+// to LDS (forming its v), issue the loads of plane k+2 into registers,
+// barrier, update plane k, barrier.  The march is unrolled by three so every
+// LDS slot is a compile-time constant.
+constexpr int ATX = 32, ATY = 8, ATHREADS = ATX * ATY;
+constexpr int APX = ATX + 3, APY = ATY + 3, APS = APX * APY;   // local x, y in [-1, AT + 1]
+constexpr int ADJ_TZ = 16;
+constexpr int APTS = (APS + ATHREADS - 1) / ATHREADS;            // halo points per thread
+
+template <typename T>
+__global__ __launch_bounds__(ATHREADS) void k_adj_tile(const AdjArgs<T> a) {
+    using C = T;
+    __shared__ T s_lg[3][3][APS], s_g[3][3][APS], s_v[3][3][APS], s_r[3][APS], s_lr[3][APS];
+    const int nx = a.nx, ny = a.ny, nz = a.nz, plane = nx * ny;
+    int bx, by, bz;
+    {
+        const int nblk = a.gx * a.gy * a.gz, b = blockIdx.x;
+        const int per = nblk / 8, rem = nblk % 8, xcd = b % 8, idx = b / 8;
+        const int t = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+        bx = t % a.gx;
+        by = (t / a.gx) % a.gy;
+        bz = t / (a.gx * a.gy);
+    }
+    const int x0 = bx * ATX, y0 = by * ATY, z0 = bz * a.tz;
+    const int W = min(ATX, nx - x0), Wy = min(ATY, ny - y0), z1 = min(z0 + a.tz, nz);
+    const int tid = threadIdx.x, lx = tid % ATX, ly = tid / ATX;
+    const bool own = lx < W && ly < Wy;
+    const int c0 = (ly + 1) * APX + (lx + 1);
+    const C rho0 = (C)a.rho0, half = (C)0.5, quarter = (C)0.25;
+    auto gidx = [&](int px, int py, int z) {
+        return wrap(z, nz) * plane + wrap(y0 + py, ny) * nx + wrap(x0 + px, nx);
+    };
+    // this thread's halo points: x in [-1, W + 1], y in [-1, Wy + 1] for the
+    // density of the next plane, x in [-1, W], y in [-1, Wy] for the rest
+    int pi[APTS], pg[APTS];
+    bool pin[APTS], pfull[APTS];
+#pragma unroll
+    for (int r = 0; r < APTS; ++r) {
+        const int i = tid + r * ATHREADS;
+        const int px = i % APX - 1, py = i / APX - 1;
+        pi[r] = i;
+        pin[r] = i < APS && px <= W + 1 && py <= Wy + 1;
+        pfull[r] = pin[r] && px <= W && py <= Wy;
+        pg[r] = pin[r] ? wrap(y0 + py, ny) * nx + wrap(x0 + px, nx) : 0;
+    }
+    T f_lg[APTS][3], f_g[APTS][3], f_lr[APTS], f_rn[APTS];
+    // loads of plane z (and the density of plane z + 1) into registers
+    auto fetch = [&](int z) {
+        const int o0 = wrap(z, nz) * plane, o1 = wrap(z + 1, nz) * plane;
+#pragma unroll
+        for (int r = 0; r < APTS; ++r) {
+            if (pin[r]) f_rn[r] = a.U[0][o1 + pg[r]];
+            if (pfull[r]) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    f_lg[r][c] = a.lam[1 + c][o0 + pg[r]];
+                    f_g[r][c] = a.U[1 + c][o0 + pg[r]];
+                }
+                f_lr[r] = a.lam[0][o0 + pg[r]];
+            }
+        }
+    };
+    // plane z into slot S (the density of plane z is in slot S already; the
+    // density of plane z + 1 goes to slot S + 1)
+    auto commit = [&](auto S_) {
+        constexpr int S = decltype(S_)::value, S1 = (S + 1) % 3;
+#pragma unroll
+        for (int r = 0; r < APTS; ++r) {
+            const int i = pi[r];
+            if (pin[r]) s_r[S1][i] = f_rn[r];
+            if (pfull[r]) {
+                const C r0 = s_r[S][i];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    s_lg[c][S][i] = f_lg[r][c];
+                    s_g[c][S][i] = f_g[r][c];
+                    const C rnb = c == 0 ? (C)s_r[S][i + 1] : (c == 1 ? (C)s_r[S][i + APX] : (C)f_rn[r]);
+                    s_v[c][S][i] = (C)f_g[r][c] / (rho0 + half * (r0 + rnb));
+                }
+                s_lr[S][i] = f_lr[r];
+            }
+        }
+    };
+    double dacc[IC_MAX_MODES];
+#pragma unroll
+    for (int m = 0; m < IC_MAX_MODES; ++m) dacc[m] = 0.0;
+
+    // update of plane k, whose slot is R (planes k - 1, k + 1 in R - 1, R + 1)
+    auto update = [&](auto R_, int k) {
+        constexpr int R = decltype(R_)::value;
+        constexpr int SK[3] = {(R + 2) % 3, R, (R + 1) % 3};
+        auto at = [&](int sa, int s, int sb, int t, int &pl) {
+            int d[3] = {0, 0, 0};
+            d[sa] += s;
+            d[sb] += t;
+            pl = SK[d[2] + 1];
+            return c0 + d[0] + d[1] * APX;
+        };
+        auto vat = [&](int c, int sa, int s, int sb, int t) {
+            int pl;
+            const int i = at(sa, s, sb, t, pl);
+            return (C)s_v[c][pl][i];
+        };
+        auto gat = [&](int c, int sa, int s, int sb, int t) {
+            int pl;
+            const int i = at(sa, s, sb, t, pl);
+            return (C)s_g[c][pl][i];
+        };
+        auto lgat = [&](int c, int sa, int s, int sb, int t) {
+            int pl;
+            const int i = at(sa, s, sb, t, pl);
+            return (C)s_lg[c][pl][i];
+        };
+        const C k_ = (C)a.k, eta = (C)a.eta, ih = (C)a.inv_h, lam_b = (C)a.lam_b;
+        auto mup_at = [&](int sa, int s) {
+            C m = 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) m += -k_ * (lgat(c, sa, s, c, -1) - lgat(c, sa, s, c, 0));
+            return m;
+        };
+        const C lr0 = (C)s_lr[SK[1]][c0];
+        const C lr1[3] = {(C)s_lr[SK[1]][c0 + 1], (C)s_lr[SK[1]][c0 + APX], (C)s_lr[SK[2]][c0]};
+        const C rj = (C)s_r[SK[1]][c0];
+        const C rn[3] = {(C)s_r[SK[1]][c0 + 1], (C)s_r[SK[1]][c0 + APX], (C)s_r[SK[2]][c0]};
+        const C mu_p = mup_at(0, 0);
+        const int j = k * plane + (y0 + ly) * nx + x0 + lx;
+        C murf[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            C mgv = -k_ * (lr0 - lr1[ax]);
+            C mvv = 0;
+            const C lgm = lgat(ax, ax, -1, ax, 0), lg0 = lgat(ax, ax, 0, ax, 0), lgp = lgat(ax, ax, 1, ax, 0);
+            const C mC0 = -k_ * (lgm - lg0);
+            const C mC1 = -k_ * (lg0 - lgp);
+            const C v0 = vat(ax, ax, 0, ax, 0), vm = vat(ax, ax, -1, ax, 0), vp = vat(ax, ax, 1, ax, 0);
+            const C g0 = gat(ax, ax, 0, ax, 0), gm = gat(ax, ax, -1, ax, 0), gp = gat(ax, ax, 1, ax, 0);
+            mgv += quarter * (v0 + vm) * mC0 + quarter * (vp + v0) * mC1;
+            mvv += quarter * (g0 + gm) * mC0 + quarter * (gp + g0) * mC1;
+            mvv += -2 * eta * ih * (mC0 - mC1);
+            mvv += -lam_b * (mu_p - mup_at(ax, 1)) * ih;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                if (b == ax) continue;
+                const C mE0 = -k_ * (lgat(ax, b, 0, b, 0) - lgat(ax, b, 1, b, 0));
+                const C mEm = -k_ * (lgat(ax, b, -1, b, 0) - lgat(ax, b, 0, b, 0));
+                const C Q0 = vat(b, b, 0, ax, 0) + vat(b, ax, 1, b, 0);
+                const C Qm = vat(b, b, -1, ax, 0) + vat(b, b, -1, ax, 1);
+                mgv += quarter * Q0 * mE0 + quarter * Qm * mEm;
+                mvv += -eta * ih * (mEm - mE0);
+                const C mF0 = -k_ * (lgat(b, ax, 0, ax, 0) - lgat(b, ax, 1, ax, 0));
+                const C mFm = -k_ * (lgat(b, b, -1, ax, 0) - lgat(b, b, -1, ax, 1));
+                const C P0 = gat(b, ax, 0, ax, 0) + gat(b, ax, 1, ax, 0);
+                const C Pm = gat(b, b, -1, ax, 0) + gat(b, b, -1, ax, 1);
+                mvv += quarter * P0 * mF0 + quarter * Pm * mFm;
+                mvv += -eta * ih * (mFm - mF0);
+            }
+            const C irf = (C)1 / (rho0 + half * (rj + rn[ax]));
+            adj_combine(a, 1 + ax, j, lg0, mgv + mvv * irf);
+            murf[ax] = -mvv * (g0 * irf) * irf;
+        }
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) a.murf[ax][j] = murf[ax];
+        a.mur[j] = (C)a.cf2 * mu_p + half * (murf[0] + murf[1] + murf[2]);
+#pragma unroll
+        for (int m = 0; m < IC_MAX_MODES; ++m) {
+            if (m >= a.nmodes) break;
+            const int ax = a.dc.axis[m];
+            dacc[m] += (double)mu_p * a.prof[m * a.pstride + (ax == 0 ? x0 + lx : (ax == 1 ? y0 + ly : k))];
+        }
+    };
+    // one plane of the march: commit plane k + 1 (slot R + 1), prefetch k + 2,
+    // update plane k (slot R)
+    auto iteration = [&](auto R_, int k) {
+        constexpr int R = decltype(R_)::value;
+        __syncthreads();
+        commit(std::integral_constant<int, (R + 1) % 3>{});
+        if (k + 2 <= z1) fetch(k + 2);
+        __syncthreads();
+        if (own) update(R_, k);
+    };
+
+    // prologue: density of z0 - 1 (slot 2), planes z0 - 1 (slot 2) and z0 (slot 0)
+    {
+#pragma unroll
+        for (int r = 0; r < APTS; ++r)
+            if (pin[r]) s_r[2][pi[r]] = a.U[0][wrap(z0 - 1, nz) * plane + pg[r]];
+    }
+    fetch(z0 - 1);
+    __syncthreads();
+    commit(std::integral_constant<int, 2>{});
+    fetch(z0);
+    __syncthreads();
+    commit(std::integral_constant<int, 0>{});
+    fetch(z0 + 1);
+    for (int k = z0; k < z1; k += 3) {
+        iteration(std::integral_constant<int, 0>{}, k);
+        if (k + 1 < z1) iteration(std::integral_constant<int, 1>{}, k + 1);
+        if (k + 2 < z1) iteration(std::integral_constant<int, 2>{}, k + 2);
+    }
+    if (a.nmodes > 0) {
+        __shared__ double s_red[IC_MAX_MODES][ATHREADS / 64];
+        const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+        for (int m = 0; m < IC_MAX_MODES; ++m) {
+            if (m >= a.nmodes) break;
+            double v = dacc[m];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) s_red[m][wave] = v;
+        }
+        __syncthreads();
+        if (tid < a.nmodes) {
+            double sum = 0.0;
+            for (int w = 0; w < ATHREADS / 64; ++w) sum += s_red[tid][w];
+            a.partial[tid * a.nbp + blockIdx.x] += a.dc.c[tid] * sum;
         }
     }
 }
@@ -2056,7 +2282,17 @@ hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *con
             x.dc.axis[m] = md.axis;
             x.dc.c[m] = cs[st] * sin(md.omega * ts[st] + md.phase);
         }
-        hipLaunchKernelGGL(k_adj_mom<T>, dim3(nb), dim3(256), 0, s, x);
+        x.nbp = adjoint_blocks(p);
+        x.tz = ADJ_TZ;
+        x.gx = (p.nx + ATX - 1) / ATX;
+        x.gy = (p.ny + ATY - 1) / ATY;
+        x.gz = (p.nz + ADJ_TZ - 1) / ADJ_TZ;
+        // FP64 tiles need 100 KB of LDS (one block per CU): the cached
+        // per-cell kernel is faster there
+        if (sizeof(T) == 4)
+            hipLaunchKernelGGL(k_adj_tile<T>, dim3(x.gx * x.gy * x.gz), dim3(ATHREADS), 0, s, x);
+        else
+            hipLaunchKernelGGL(k_adj_mom<T>, dim3(nb), dim3(256), 0, s, x);
         hipLaunchKernelGGL(k_adj_rho<T>, dim3(nb), dim3(256), 0, s, x);
     }
     hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, w.st, (int64_t)c->step);

@@ -79,7 +79,13 @@ struct AdjWorkspace {
     void *L2[4], *L1[4], *acc[4], *murf[3], *mur;
     double *partial;   // [IC_MAX_MODES][adjoint_blocks]
 };
-inline int adjoint_blocks(const ic_params &p) { return (int)(((size_t)p.nx * p.ny * p.nz + 255) / 256); }
+// Partial-sum slots per mode: at least one per block of either momentum pass
+// (256 cells per block, or 32 x 8 x 16-cell tiles).
+inline int adjoint_blocks(const ic_params &p) {
+    const long cells = ((long)p.nx * p.ny * p.nz + 255) / 256;
+    const long tiles = (long)((p.nx + 31) / 32) * ((p.ny + 7) / 8) * ((p.nz + 15) / 16);
+    return (int)(cells > tiles ? cells : tiles);
+}
 size_t adjoint_workspace_bytes(const ic_params &p);
 void carve_adjoint(const ic_params &p, char *base, AdjWorkspace &aw);
 
