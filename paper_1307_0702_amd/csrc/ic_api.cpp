@@ -480,8 +480,11 @@ int ic_step(ic_ctx *c, int64_t nsteps) {
     int rc = check_bound(c);
     if (rc != IC_OK) return rc;
     if (nsteps < 0) return fail(c, IC_E_ARG, "nsteps < 0");
+    // The side stream pays for its event round trips only on large grids;
+    // small grids are launch-latency-bound and step on one stream.
+    const bool overlap = (double)c->p.nx * c->p.ny * c->p.nz >= 1048576.0;
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipError_t e = launch_step(c, true, s == 0, s == nsteps - 1);
+        hipError_t e = launch_step(c, overlap, s == 0, s == nsteps - 1);
         if (e != hipSuccess) return hip_fail(c, e, "step launch");
         c->step += 1;
         if (c->np > 0) c->nsamples += 1;
