@@ -55,6 +55,9 @@ class ICError(RuntimeError):
 def load_library(path=LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"libic.so not built: {path} is missing (run __graft_entry__.build())")
+    # torch first: libic.so then binds to the HIP runtime torch has loaded,
+    # so the streams and memory torch hands over belong to the same runtime
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     dp = ctypes.POINTER(ctypes.c_double)
