@@ -9,9 +9,10 @@ on the HIP path, which the parity tests tie to the oracle step by step.
   The mean spring force is compared with Gor'kov's
   F = c_f^2 drho^2 V k / (4 rho0) (f1 + 3/2 f2) sin(2 k z), using the measured
   wave amplitude.  f1 = 1 - kappa_p/kappa_f, f2 = 2 m_e / (2 m_e + 3 rho0 V).
-  The springs are soft (tether frequency far below the drive frequency), so
-  the particles oscillate with the wave as Gor'kov's force assumes.
-  Regime: the paper's nu/(c h) = 0.0125.
+  The springs are soft (tether frequency a sixth of the drive frequency at
+  every box size), so the particles oscillate with the wave as Gor'kov's
+  force assumes.  Regime: the paper's nu/(c h) = 0.0125; box sizes 32h to 64h
+  for the finite-size check (Sec. VI studies the same dependence).
 * Equilibrium fluctuations (Sec. IV E; App. A, convergence analysis):
   Var(drho) = rho0 kT/(c_f^2 h^3) per cell, Var(v) = kT/(rho0 h^3) per face,
   Var(J rho) = rho0 kT/(c_p^2 V) at a particle, and particle equipartition
@@ -64,11 +65,18 @@ def _amplitude(sim, w, nT):
     return math.sqrt(2.0 * np.mean(a2))
 
 
-def radiation_force(me, kappa_ratio, eta=0.0125, amp=1e-3, ks=0.02, nwarm=40000, nper=4,
+def radiation_force(me, kappa_ratio, eta=0.0125, amp=1e-3, ks=None, nwarm=None, nper=4,
                     prec="fp64", L=32):
-    """Mean tether force on the symmetric pair and Gor'kov's value for it."""
+    """Mean tether force on the symmetric pair and Gor'kov's value for it.
+    The tether is soft, k_s = m_p (omega/6)^2 (reading R9), so its frequency
+    stays a sixth of the drive frequency at every box size; the warm-up
+    grows with the acoustic damping time, as L^2."""
     fl = W.Fluid(L, L, L, kT=0.0, seed=1, eta=eta, zeta=eta)
     mode, nT = W.modal_drive(fl, amp)
+    if ks is None:
+        ks = (me + fl.rho0 * V) * (mode.omega / 6) ** 2
+    if nwarm is None:
+        nwarm = int(40000 * (L / 32) ** 2)
     drho, g = W.standing_wave_fields(fl, amp, omega=mode.omega)
     qeq = np.array([[3 * L / 8, L / 2, L / 2], [L - 3 * L / 8, 0.0, 0.0]])
     k = 2 * math.pi / L
@@ -108,18 +116,33 @@ def test_radiation_force_dipolar():
 
 def test_radiation_force_monopolar():
     # c_p = 2 c_f: kappa_p = kappa_f / 4, f1 = 0.75.  The model's monopolar
-    # force falls below Gor'kov at L = 32h (finite size of the blob relative
-    # to the wavelength and the images of the periodic box).
+    # force falls about 10% below Gor'kov (the paper reports deviations of
+    # that size for the monopolar term).
     f, gork, _, _ = radiation_force(me=0.0, kappa_ratio=0.25)
     assert np.all(np.sign(f[:, 0]) == np.sign(gork))
-    assert np.allclose(f[:, 0], gork, rtol=0.20)
+    r = f[:, 0] / gork
+    assert np.all((r > 0.85) & (r < 0.95)), r
+
+
+@pytest.mark.parametrize("L", [48, 64])
+def test_radiation_force_finite_size(L):
+    # Box sizes 48h and 64h (kR_a = 0.16 and 0.12 against 0.24 at 32h): the
+    # ratios to Gor'kov stay where they are at 32h, so neither the dipolar
+    # agreement nor the monopolar deficit is a finite-size effect of the box.
+    f, gork, _, _ = radiation_force(me=V, kappa_ratio=1.0, L=L, nper=8)
+    rd = f[:, 0] / gork
+    f, gork, _, _ = radiation_force(me=0.0, kappa_ratio=0.25, L=L, nper=8)
+    rm = f[:, 0] / gork
+    print(f"  L = {L}: dipolar ratio {rd}, monopolar ratio {rm}", flush=True)
+    assert np.all(np.abs(rd - 1) < 0.05), rd
+    assert np.all((rm > 0.85) & (rm < 0.95)), rm
 
 
 def test_radiation_force_negative_contrast():
     # m_p = rho0 V / 2, kappa_p = 2 kappa_f: f1 + 3/2 f2 = -1.75
     f, gork, _, _ = radiation_force(me=-0.5 * V, kappa_ratio=2.0)
     assert np.all(np.sign(f[:, 0]) == np.sign(gork))
-    assert np.allclose(f[:, 0], gork, rtol=0.12)
+    assert np.allclose(f[:, 0], gork, rtol=0.06)
 
 
 def test_radiation_force_neutral_particle_and_amplitude_scaling():
@@ -128,7 +151,7 @@ def test_radiation_force_neutral_particle_and_amplitude_scaling():
     # dipolar force of an m_p = 2 rho0 V particle (f2 = 0.4) in the same wave
     L = 32
     ref = a * a * V * (2 * math.pi / L) / 4 * 1.5 * 0.4
-    assert np.all(np.abs(f0[:, 0]) < 0.12 * ref)
+    assert np.all(np.abs(f0[:, 0]) < 0.08 * ref)
     # the force is second order in the wave amplitude
     fa, _, _, _ = radiation_force(me=V, kappa_ratio=1.0)
     fb, _, _, _ = radiation_force(me=V, kappa_ratio=1.0, amp=5e-4)
@@ -141,7 +164,7 @@ def test_fp32_averaged_force_against_fp64():
     # FP32 rounding of the momentum updates does not telescope: the total
     # momentum random-walks (about 6e-11 per cell-update at |g| ~ 1e-3, 2.6e-6
     # after 2e4 steps at 32^3), and the uniform flow it leaves drags the
-    # tethered pair.  That bias, about 4e-3 of the force here, falls as
+    # tethered pair.  That bias, about 6e-4 of the force here, falls as
     # 1/sqrt(cells) for a fixed force and run length.
     kw = dict(me=V, kappa_ratio=0.5, eta=0.5, nwarm=20000, nper=4)
     f64, _, m64, _ = radiation_force(prec="fp64", **kw)
@@ -151,7 +174,7 @@ def test_fp32_averaged_force_against_fp64():
           f"momentum FP32 {m32[0]:.2e}, FP64 {m64[0]:.2e}", flush=True)
     assert np.all(np.sign(f32[:, 0]) == np.sign(f64[:, 0]))
     assert abs(m64[0]) < 1e-9 and abs(m32[0]) < 1e-4
-    assert rel < 1e-2
+    assert rel < 2e-3
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
