@@ -145,9 +145,13 @@ int ic_get_tile(ic_ctx *ctx, int32_t *tz);
 
 /* Advances the bound state by nsteps IC time steps (App. A, "Temporal
  * discretization", substeps 1-7, with the three SSP-RK3 stages of the fluid
- * update).  Asynchronous.  A step whose no-slip impulse finds m_e + m_f <= 0
- * raises a device flag reported by the next synchronising call as
- * IC_E_MASS. */
+ * update).  Asynchronous.  On grids of 2^20 cells or more, part of each step
+ * (the particle prologue and, in FP32, the next step's noise) runs on a
+ * second stream owned by the context, which every step joins back into the
+ * context stream before it ends, so ordering against the caller's work on
+ * that stream is unchanged.  A step whose no-slip impulse finds
+ * m_e + m_f <= 0 raises a device flag reported by the next synchronising
+ * call as IC_E_MASS. */
 int ic_step(ic_ctx *ctx, int64_t nsteps);
 
 /* Averaging operator J (Sec. II, Eq. Jdis; staggered positions of App. A):
