@@ -1435,7 +1435,7 @@ __global__ __launch_bounds__(SP_THREADS) void k_sparse(const SparseArgs<T> a) {
 // the stage kernel, App. A) applied to an adjoint state lambda, one cell per
 // thread, neighbours read through the caches, arithmetic in the context
 // precision.
-//   k_adj_mom: the momentum part mu_g (incl. the v = g / rho_face chain), the
+//   k_adj_tile: the momentum part mu_g (incl. the v = g / rho_face chain), the
 //     face-density adjoints mu_rf = d/d rho_face and mu_p (sum of the
 //     centre-flux adjoints); writes the momentum components of the RK
 //     combination, mu_rf and mu_rpart = c_f^2 mu_p + (sum_a mu_rf_a) / 2,
@@ -1486,44 +1486,6 @@ __device__ __forceinline__ void adj_combine(const AdjArgs<T> &a, int c, int j, T
     }
 }
 
-// Wrapped coordinates of a cell and its neighbours at offsets -1..+2 along
-// each axis; flat index of the cell shifted by an offset vector.  The offset
-// vectors below are compile-time constants once the axis loops unroll.
-struct Nbr {
-    int X[4], Y[4], Z[4];   // coordinate + (k - 1), periodic
-    int nx, nxy;
-    __device__ __forceinline__ Nbr(int x, int y, int z, int nx_, int ny_, int nz_) : nx(nx_), nxy(nx_ * ny_) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            int a = x + k - 1, b = y + k - 1, c = z + k - 1;
-            a += a < 0 ? nx_ : 0;
-            a -= a >= nx_ ? nx_ : 0;
-            b += b < 0 ? ny_ : 0;
-            b -= b >= ny_ ? ny_ : 0;
-            c += c < 0 ? nz_ : 0;
-            c -= c >= nz_ ? nz_ : 0;
-            X[k] = a;
-            Y[k] = b;
-            Z[k] = c * nxy;
-        }
-    }
-    // index of the cell shifted s along axis a and t along axis b
-    __device__ __forceinline__ int at(int a, int s, int b = 0, int t = 0) const {
-        int d[3] = {0, 0, 0};
-        d[a] += s;
-        d[b] += t;
-        return Z[d[2] + 1] + Y[d[1] + 1] * nx + X[d[0] + 1];
-    }
-    // same, shifted once more by +1 along axis c
-    __device__ __forceinline__ int at3(int a, int s, int b, int t, int c) const {
-        int d[3] = {0, 0, 0};
-        d[a] += s;
-        d[b] += t;
-        d[c] += 1;
-        return Z[d[2] + 1] + Y[d[1] + 1] * nx + X[d[0] + 1];
-    }
-};
-
 __device__ __forceinline__ void cell_of(int j, int nx, int ny, int &x, int &y, int &z) {
     const int r = j / nx;
     x = j - r * nx;
@@ -1531,124 +1493,28 @@ __device__ __forceinline__ void cell_of(int j, int nx, int ny, int &x, int &y, i
     y = r - z * ny;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_adj_mom(const AdjArgs<T> a) {
-    using C = T;
-    const int ncell = a.nx * a.ny * a.nz;
-    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    const bool live = j < ncell;
-    int x = 0, y = 0, z = 0;
-    C mu_p = 0;
-    if (live) {
-        cell_of(j, a.nx, a.ny, x, y, z);
-        const Nbr N(x, y, z, a.nx, a.ny, a.nz);
-        const C k = (C)a.k, eta = (C)a.eta, ih = (C)a.inv_h, rho0 = (C)a.rho0, half = (C)0.5,
-                quarter = (C)0.25, lam_b = (C)a.lam_b;
-        const T *__restrict__ R = a.U[0];
-        // v_c = g_c / rho_face_c at the cell shifted (s along sa, t along sb)
-        auto vat = [&](int c, int sa, int s, int sb, int t) {
-            const C rf = rho0 + half * (R[N.at(sa, s, sb, t)] + R[N.at3(sa, s, sb, t, c)]);
-            return a.U[1 + c][N.at(sa, s, sb, t)] / rf;
-        };
-        auto gat = [&](int c, int sa, int s, int sb, int t) { return (C)a.U[1 + c][N.at(sa, s, sb, t)]; };
-        auto lgat = [&](int c, int sa, int s, int sb, int t) { return (C)a.lam[1 + c][N.at(sa, s, sb, t)]; };
-        // mu_p at the cell shifted s along sa: sum over c of -k (lg_c[i - e_c] - lg_c[i])
-        auto mup_at = [&](int sa, int s) {
-            C m = 0;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) m += -k * (lgat(c, sa, s, c, -1) - lgat(c, sa, s, c, 0));
-            return m;
-        };
-        mu_p = mup_at(0, 0);
-        C murf[3];
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            // mass: -k (lr[j] - lr[j+ax])
-            C mgv = -k * ((C)a.lam[0][j] - (C)a.lam[0][N.at(ax, 1)]);
-            C mvv = 0;
-            // centre flux C_ax at cells j and j+ax: muC(i) = -k (lg_ax[i-ax] - lg_ax[i])
-            const C lgm = lgat(ax, ax, -1, ax, 0), lg0 = lgat(ax, ax, 0, ax, 0), lgp = lgat(ax, ax, 1, ax, 0);
-            const C mC0 = -k * (lgm - lg0);
-            const C mC1 = -k * (lg0 - lgp);
-            // B(i) = v_ax(i) + v_ax(i-ax); A(i) = (g_ax(i) + g_ax(i-ax)) / 4
-            const C v0 = vat(ax, ax, 0, ax, 0), vm = vat(ax, ax, -1, ax, 0), vp = vat(ax, ax, 1, ax, 0);
-            const C g0 = gat(ax, ax, 0, ax, 0), gm = gat(ax, ax, -1, ax, 0), gp = gat(ax, ax, 1, ax, 0);
-            mgv += quarter * (v0 + vm) * mC0 + quarter * (vp + v0) * mC1;
-            mvv += quarter * (g0 + gm) * mC0 + quarter * (gp + g0) * mC1;
-            mvv += -2 * eta * ih * (mC0 - mC1);
-            // bulk: mu_div(i) = -lam_b mu_p(i); mu_v_ax += (mu_div(j) - mu_div(j+ax)) / h
-            mvv += -lam_b * (mu_p - mup_at(ax, 1)) * ih;
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                if (b == ax) continue;
-                // edge flux E_{ax b}(i) = (g_ax(i) + g_ax(i+b)) (v_b(i) + v_b(i+ax)) / 4 - visc;
-                // muE(i) = -k (lg_ax(i) - lg_ax(i+b)) reaches g_ax at j from i = j and i = j - b
-                const C mE0 = -k * (lgat(ax, b, 0, b, 0) - lgat(ax, b, 1, b, 0));
-                const C mEm = -k * (lgat(ax, b, -1, b, 0) - lgat(ax, b, 0, b, 0));
-                const C Q0 = vat(b, b, 0, ax, 0) + vat(b, ax, 1, b, 0);
-                const C Qm = vat(b, b, -1, ax, 0) + vat(b, b, -1, ax, 1);
-                mgv += quarter * Q0 * mE0 + quarter * Qm * mEm;
-                // viscous part of E_{ax b} in v_ax: -eta/h (v_ax(i+b) - v_ax(i))
-                mvv += -eta * ih * (mEm - mE0);
-                // edge flux E_{b ax}(i) = (g_b(i) + g_b(i+ax)) (v_ax(i) + v_ax(i+b)) / 4 - visc;
-                // muF(i) = -k (lg_b(i) - lg_b(i+ax)) reaches v_ax at j from i = j and i = j - b
-                const C mF0 = -k * (lgat(b, ax, 0, ax, 0) - lgat(b, ax, 1, ax, 0));
-                const C mFm = -k * (lgat(b, b, -1, ax, 0) - lgat(b, b, -1, ax, 1));
-                const C P0 = gat(b, ax, 0, ax, 0) + gat(b, ax, 1, ax, 0);
-                const C Pm = gat(b, b, -1, ax, 0) + gat(b, b, -1, ax, 1);
-                mvv += quarter * P0 * mF0 + quarter * Pm * mFm;
-                // viscous part of E_{b ax} in v_ax: -eta/h (v_ax(i+b) - v_ax(i))
-                mvv += -eta * ih * (mFm - mF0);
-            }
-            // v_ax = g_ax / rf_ax
-            const C irf = (C)1 / (rho0 + half * (R[j] + R[N.at(ax, 1)]));
-            adj_combine(a, 1 + ax, j, lg0, mgv + mvv * irf);
-            murf[ax] = -mvv * (g0 * irf) * irf;
-        }
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) a.murf[ax][j] = murf[ax];
-        a.mur[j] = (C)a.cf2 * mu_p + half * (murf[0] + murf[1] + murf[2]);
-    }
-    if (a.nmodes > 0) {
-        // per-block partials of coef_m sum_j mu_p(j) prof_m(j), fixed order
-        __shared__ double s_red[IC_MAX_MODES][4];
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-        for (int m = 0; m < IC_MAX_MODES; ++m) {
-            if (m >= a.nmodes) break;
-            const int ax = a.dc.axis[m];
-            double v = live ? (double)mu_p * a.prof[m * a.pstride + (ax == 0 ? x : (ax == 1 ? y : z))] : 0.0;
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-            if (lane == 0) s_red[m][wave] = v;
-        }
-        __syncthreads();
-        if (threadIdx.x < (unsigned)a.nmodes) {
-            const int m = threadIdx.x;
-            const double sum = ((s_red[m][0] + s_red[m][1]) + s_red[m][2]) + s_red[m][3];
-            a.partial[m * a.nbp + blockIdx.x] += a.dc.c[m] * sum;
-        }
-    }
-}
-
-// Tiled momentum pass (same arithmetic as k_adj_mom): a tile of ATX x ATY
+// Momentum pass of the transposed stage increment: a tile of ATX x ATY
 // columns marches over tz planes in z.  LDS holds three planes (k-1, k, k+1)
-// of lambda_g, g, v = g / rho_face and lambda_rho, and three density planes
-// (k, k+1, k+2), each with a one-cell halo (two on the high side for
-// density), so a cell's neighbour reads come from LDS and each velocity is
-// divided out once per point.  Per plane k: commit the prefetched plane k+1
-// to LDS (forming its v), issue the loads of plane k+2 into registers,
-// barrier, update plane k, barrier.  The march is unrolled by three so every
-// LDS slot is a compile-time constant.
+// of lambda_g, g and v = g / rho_face and three density planes (k, k+1, k+2)
+// over the tile plus a one-cell halo, so a cell's neighbour reads come from
+// LDS and each velocity is divided out once per point.  lambda_rho is read
+// from memory (four values per cell), and the two density values one cell
+// beyond the halo that the halo's own velocities need come from registers:
+// 40.8 KB of LDS in FP32 (4 blocks per CU), 81.6 KB in FP64 (2).  Per plane
+// k: commit the prefetched plane k+1 to LDS (forming its v), issue the loads
+// of plane k+2 into registers, barrier, update plane k, barrier.  The march
+// is unrolled by three so every LDS slot is a compile-time constant.
 constexpr int ATX = 32, ATY = 8, ATHREADS = ATX * ATY;
-constexpr int APX = ATX + 3, APY = ATY + 3, APS = APX * APY;   // local x, y in [-1, AT + 1]
+constexpr int APX = ATX + 2, APY = ATY + 2, APS = APX * APY;   // local x, y in [-1, AT]
 constexpr int ADJ_TZ = 16;
 constexpr int APTS = (APS + ATHREADS - 1) / ATHREADS;            // halo points per thread
 
 template <typename T>
-__global__ __launch_bounds__(ATHREADS) void k_adj_tile(const AdjArgs<T> a) {
+__global__ __launch_bounds__(ATHREADS)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_adj_tile(const AdjArgs<T> a) {
     using C = T;
-    __shared__ T s_lg[3][3][APS], s_g[3][3][APS], s_v[3][3][APS], s_r[3][APS], s_lr[3][APS];
+    __shared__ __attribute__((aligned(16))) T s_lg[3][3][APS];   // also the reduction scratch
+    __shared__ T s_g[3][3][APS], s_v[3][3][APS], s_r[3][APS];
     const int nx = a.nx, ny = a.ny, nz = a.nz, plane = nx * ny;
     int bx, by, bz;
     {
@@ -1664,38 +1530,43 @@ __global__ __launch_bounds__(ATHREADS) void k_adj_tile(const AdjArgs<T> a) {
     const int tid = threadIdx.x, lx = tid % ATX, ly = tid / ATX;
     const bool own = lx < W && ly < Wy;
     const int c0 = (ly + 1) * APX + (lx + 1);
+    const int own_xy = own ? (y0 + ly) * nx + x0 + lx : 0;
+    const int own_x1 = own ? (y0 + ly) * nx + wrap(x0 + lx + 1, nx) : 0;
+    const int own_y1 = own ? wrap(y0 + ly + 1, ny) * nx + x0 + lx : 0;
     const C rho0 = (C)a.rho0, half = (C)0.5, quarter = (C)0.25;
-    auto gidx = [&](int px, int py, int z) {
-        return wrap(z, nz) * plane + wrap(y0 + py, ny) * nx + wrap(x0 + px, nx);
-    };
-    // this thread's halo points: x in [-1, W + 1], y in [-1, Wy + 1] for the
-    // density of the next plane, x in [-1, W], y in [-1, Wy] for the rest
-    int pi[APTS], pg[APTS];
-    bool pin[APTS], pfull[APTS];
+    // this thread's halo points (x in [-1, W], y in [-1, Wy]); points on the
+    // high edges also need the density one cell further out
+    int pi[APTS], pg[APTS], pgx[APTS], pgy[APTS];
+    bool pin[APTS], pex[APTS], pey[APTS];
 #pragma unroll
     for (int r = 0; r < APTS; ++r) {
         const int i = tid + r * ATHREADS;
         const int px = i % APX - 1, py = i / APX - 1;
         pi[r] = i;
-        pin[r] = i < APS && px <= W + 1 && py <= Wy + 1;
-        pfull[r] = pin[r] && px <= W && py <= Wy;
-        pg[r] = pin[r] ? wrap(y0 + py, ny) * nx + wrap(x0 + px, nx) : 0;
+        pin[r] = i < APS && px <= W && py <= Wy;
+        pex[r] = pin[r] && px == W;
+        pey[r] = pin[r] && py == Wy;
+        const int gx = wrap(x0 + px, nx), gy = wrap(y0 + py, ny);
+        pg[r] = pin[r] ? gy * nx + gx : 0;
+        pgx[r] = pex[r] ? gy * nx + wrap(x0 + px + 1, nx) : 0;
+        pgy[r] = pey[r] ? wrap(y0 + py + 1, ny) * nx + gx : 0;
     }
-    T f_lg[APTS][3], f_g[APTS][3], f_lr[APTS], f_rn[APTS];
-    // loads of plane z (and the density of plane z + 1) into registers
+    T f_lg[APTS][3], f_g[APTS][3], f_rn[APTS], f_rx[APTS], f_ry[APTS];
+    // loads of plane z, the density of plane z + 1, and the edge densities of plane z
     auto fetch = [&](int z) {
         const int o0 = wrap(z, nz) * plane, o1 = wrap(z + 1, nz) * plane;
 #pragma unroll
         for (int r = 0; r < APTS; ++r) {
-            if (pin[r]) f_rn[r] = a.U[0][o1 + pg[r]];
-            if (pfull[r]) {
+            if (pin[r]) {
+                f_rn[r] = a.U[0][o1 + pg[r]];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     f_lg[r][c] = a.lam[1 + c][o0 + pg[r]];
                     f_g[r][c] = a.U[1 + c][o0 + pg[r]];
                 }
-                f_lr[r] = a.lam[0][o0 + pg[r]];
             }
+            if (pex[r]) f_rx[r] = a.U[0][o0 + pgx[r]];
+            if (pey[r]) f_ry[r] = a.U[0][o0 + pgy[r]];
         }
     };
     // plane z into slot S (the density of plane z is in slot S already; the
@@ -1705,23 +1576,25 @@ __global__ __launch_bounds__(ATHREADS) void k_adj_tile(const AdjArgs<T> a) {
 #pragma unroll
         for (int r = 0; r < APTS; ++r) {
             const int i = pi[r];
-            if (pin[r]) s_r[S1][i] = f_rn[r];
-            if (pfull[r]) {
+            if (pin[r]) {
+                s_r[S1][i] = f_rn[r];
                 const C r0 = s_r[S][i];
+                const C rx = pex[r] ? (C)f_rx[r] : (C)s_r[S][i + 1];
+                const C ry = pey[r] ? (C)f_ry[r] : (C)s_r[S][i + APX];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     s_lg[c][S][i] = f_lg[r][c];
                     s_g[c][S][i] = f_g[r][c];
-                    const C rnb = c == 0 ? (C)s_r[S][i + 1] : (c == 1 ? (C)s_r[S][i + APX] : (C)f_rn[r]);
+                    const C rnb = c == 0 ? rx : (c == 1 ? ry : (C)f_rn[r]);
                     s_v[c][S][i] = (C)f_g[r][c] / (rho0 + half * (r0 + rnb));
                 }
-                s_lr[S][i] = f_lr[r];
             }
         }
     };
     double dacc[IC_MAX_MODES];
 #pragma unroll
     for (int m = 0; m < IC_MAX_MODES; ++m) dacc[m] = 0.0;
+    C q_lr[4];   // lambda_rho of the own cell and its +x, +y, +z neighbours
 
     // update of plane k, whose slot is R (planes k - 1, k + 1 in R - 1, R + 1)
     auto update = [&](auto R_, int k) {
@@ -1756,12 +1629,12 @@ __global__ __launch_bounds__(ATHREADS) void k_adj_tile(const AdjArgs<T> a) {
             for (int c = 0; c < 3; ++c) m += -k_ * (lgat(c, sa, s, c, -1) - lgat(c, sa, s, c, 0));
             return m;
         };
-        const C lr0 = (C)s_lr[SK[1]][c0];
-        const C lr1[3] = {(C)s_lr[SK[1]][c0 + 1], (C)s_lr[SK[1]][c0 + APX], (C)s_lr[SK[2]][c0]};
+        const C lr0 = q_lr[0];
+        const C lr1[3] = {q_lr[1], q_lr[2], q_lr[3]};
         const C rj = (C)s_r[SK[1]][c0];
         const C rn[3] = {(C)s_r[SK[1]][c0 + 1], (C)s_r[SK[1]][c0 + APX], (C)s_r[SK[2]][c0]};
         const C mu_p = mup_at(0, 0);
-        const int j = k * plane + (y0 + ly) * nx + x0 + lx;
+        const int j = k * plane + own_xy;
         C murf[3];
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
@@ -1806,13 +1679,20 @@ __global__ __launch_bounds__(ATHREADS) void k_adj_tile(const AdjArgs<T> a) {
             dacc[m] += (double)mu_p * a.prof[m * a.pstride + (ax == 0 ? x0 + lx : (ax == 1 ? y0 + ly : k))];
         }
     };
-    // one plane of the march: commit plane k + 1 (slot R + 1), prefetch k + 2,
-    // update plane k (slot R)
+    // one plane of the march: commit plane k + 1 (slot R + 1), prefetch k + 2
+    // and the own lambda_rho values of plane k, update plane k (slot R)
     auto iteration = [&](auto R_, int k) {
         constexpr int R = decltype(R_)::value;
         __syncthreads();
         commit(std::integral_constant<int, (R + 1) % 3>{});
         if (k + 2 <= z1) fetch(k + 2);
+        if (own) {
+            const int o = k * plane;
+            q_lr[0] = (C)a.lam[0][o + own_xy];
+            q_lr[1] = (C)a.lam[0][o + own_x1];
+            q_lr[2] = (C)a.lam[0][o + own_y1];
+            q_lr[3] = (C)a.lam[0][wrap(k + 1, nz) * plane + own_xy];
+        }
         __syncthreads();
         if (own) update(R_, k);
     };
@@ -1836,7 +1716,9 @@ __global__ __launch_bounds__(ATHREADS) void k_adj_tile(const AdjArgs<T> a) {
         if (k + 2 < z1) iteration(std::integral_constant<int, 2>{}, k + 2);
     }
     if (a.nmodes > 0) {
-        __shared__ double s_red[IC_MAX_MODES][ATHREADS / 64];
+        // per-block partials in a fixed order; the reduction reuses LDS
+        __syncthreads();
+        double(*s_red)[ATHREADS / 64] = reinterpret_cast<double(*)[ATHREADS / 64]>(&s_lg[0][0][0]);
         const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
         for (int m = 0; m < IC_MAX_MODES; ++m) {
@@ -2181,7 +2063,7 @@ hipError_t sums_impl(ic_ctx *c, double *host4) {
 
 }  // namespace
 
-// Reverse of one deterministic particle-free step (see k_adj_mom).  The
+// Reverse of one deterministic particle-free step (see k_adj_tile).  The
 // stage inputs U1, U2 of step n are recomputed from U^n with the forward
 // stage kernels into the workspace stage buffers.
 template <typename T>
@@ -2287,12 +2169,7 @@ hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *con
         x.gx = (p.nx + ATX - 1) / ATX;
         x.gy = (p.ny + ATY - 1) / ATY;
         x.gz = (p.nz + ADJ_TZ - 1) / ADJ_TZ;
-        // FP64 tiles need 100 KB of LDS (one block per CU): the cached
-        // per-cell kernel is faster there
-        if (sizeof(T) == 4)
-            hipLaunchKernelGGL(k_adj_tile<T>, dim3(x.gx * x.gy * x.gz), dim3(ATHREADS), 0, s, x);
-        else
-            hipLaunchKernelGGL(k_adj_mom<T>, dim3(nb), dim3(256), 0, s, x);
+        hipLaunchKernelGGL(k_adj_tile<T>, dim3(x.gx * x.gy * x.gz), dim3(ATHREADS), 0, s, x);
         hipLaunchKernelGGL(k_adj_rho<T>, dim3(nb), dim3(256), 0, s, x);
     }
     hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, w.st, (int64_t)c->step);
