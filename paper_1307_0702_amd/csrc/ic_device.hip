@@ -1509,6 +1509,11 @@ constexpr int APX = ATX + 2, APY = ATY + 2, APS = APX * APY;   // local x, y in 
 constexpr int ADJ_TZ = 16;
 constexpr int APTS = (APS + ATHREADS - 1) / ATHREADS;            // halo points per thread
 
+// Reciprocal for the adjoint's v = g / rho_face: the hardware estimate
+// (1 ulp) in FP32, a correctly rounded division in FP64.
+__device__ __forceinline__ float adj_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double adj_rcp(double x) { return 1.0 / x; }
+
 template <typename T>
 __global__ __launch_bounds__(ATHREADS)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_adj_tile(const AdjArgs<T> a) {
@@ -1586,7 +1591,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_adj_tile(con
                     s_lg[c][S][i] = f_lg[r][c];
                     s_g[c][S][i] = f_g[r][c];
                     const C rnb = c == 0 ? rx : (c == 1 ? ry : (C)f_rn[r]);
-                    s_v[c][S][i] = (C)f_g[r][c] / (rho0 + half * (r0 + rnb));
+                    s_v[c][S][i] = (C)f_g[r][c] * adj_rcp(rho0 + half * (r0 + rnb));
                 }
             }
         }
@@ -1665,7 +1670,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_adj_tile(con
                 mvv += quarter * P0 * mF0 + quarter * Pm * mFm;
                 mvv += -eta * ih * (mFm - mF0);
             }
-            const C irf = (C)1 / (rho0 + half * (rj + rn[ax]));
+            const C irf = adj_rcp(rho0 + half * (rj + rn[ax]));
             adj_combine(a, 1 + ax, j, lg0, mgv + mvv * irf);
             murf[ax] = -mvv * (g0 * irf) * irf;
         }
