@@ -179,15 +179,17 @@ def test_radiation_force_neutral_particle_and_amplitude_scaling():
     assert np.allclose(fb[:, 0] / fa[:, 0], 0.25, rtol=0.03)
 
 
-def test_fp32_averaged_force_against_fp64():
+@pytest.mark.parametrize("amp,bound", [(1e-3, 1e-3), (1e-2, 1e-4)])
+def test_fp32_averaged_force_against_fp64(amp, bound):
     # Deterministic run (kT = 0): FP32 storage of the fields as deviations
     # from rho0 with FP64 particle state and accumulators, against all-FP64.
-    # FP32 rounding of the momentum updates does not telescope: the total
-    # momentum random-walks (about 6e-11 per cell-update at |g| ~ 1e-3, 2.6e-6
-    # after 2e4 steps at 32^3), and the uniform flow it leaves drags the
-    # tethered pair.  That bias, about 6e-4 of the force here, falls as
-    # 1/sqrt(cells) for a fixed force and run length.
-    kw = dict(me=V, kappa_ratio=0.5, eta=0.5, nwarm=20000, nper=4)
+    # The radiation force is second order in the wave amplitude while the
+    # fluxes it comes from are first order, so FP32 rounding of those fluxes
+    # is amplified by 1/amplitude in the averaged force: 6.4e-4 relative at
+    # drho = 1e-3, 8.7e-5 at the paper-scale drho = 1e-2 (measured).  The FP32
+    # momentum drift (~1e-8 here) is not the cause: removing it every 10
+    # steps leaves the difference unchanged.
+    kw = dict(me=V, kappa_ratio=0.5, eta=0.5, nwarm=20000, nper=4, amp=amp)
     f64, _, m64, _ = radiation_force(prec="fp64", **kw)
     f32, _, m32, _ = radiation_force(prec="fp32", **kw)
     rel = np.max(np.abs(f32[:, 0] - f64[:, 0])) / np.max(np.abs(f64[:, 0]))
@@ -195,7 +197,7 @@ def test_fp32_averaged_force_against_fp64():
           f"momentum FP32 {m32[0]:.2e}, FP64 {m64[0]:.2e}", flush=True)
     assert np.all(np.sign(f32[:, 0]) == np.sign(f64[:, 0]))
     assert abs(m64[0]) < 1e-9 and abs(m32[0]) < 1e-4
-    assert rel < 2e-3
+    assert rel < bound
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
