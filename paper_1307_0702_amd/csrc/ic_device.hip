@@ -1494,7 +1494,7 @@ __device__ __forceinline__ void cell_of(int j, int nx, int ny, int &x, int &y, i
 }
 
 // Momentum pass of the transposed stage increment: a tile of ATX x ATY
-// columns marches over tz planes in z.  LDS holds three planes (k-1, k, k+1)
+// columns marches over tz = ADJ_TZ planes in z.  LDS holds three planes (k-1, k, k+1)
 // of lambda_g, g and v = g / rho_face and three density planes (k, k+1, k+2)
 // over the tile plus a one-cell halo, so a cell's neighbour reads come from
 // LDS and each velocity is divided out once per point.  lambda_rho is read
@@ -1506,7 +1506,7 @@ __device__ __forceinline__ void cell_of(int j, int nx, int ny, int &x, int &y, i
 // is unrolled by three so every LDS slot is a compile-time constant.
 constexpr int ATX = 32, ATY = 8, ATHREADS = ATX * ATY;
 constexpr int APX = ATX + 2, APY = ATY + 2, APS = APX * APY;   // local x, y in [-1, AT]
-constexpr int ADJ_TZ = 16;
+constexpr int ADJ_TZ = 32;
 constexpr int APTS = (APS + ATHREADS - 1) / ATHREADS;            // halo points per thread
 
 // Reciprocal for the adjoint's v = g / rho_face: the hardware estimate

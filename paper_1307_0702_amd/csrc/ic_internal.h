@@ -79,8 +79,9 @@ struct AdjWorkspace {
     void *L2[4], *L1[4], *acc[4], *murf[3], *mur;
     double *partial;   // [IC_MAX_MODES][adjoint_blocks]
 };
-// Partial-sum slots per mode: at least one per block of either momentum pass
-// (256 cells per block, or 32 x 8 x 16-cell tiles).
+// Partial-sum slots per mode: at least one per block of the momentum pass
+// (tiles of 32 x 8 columns and at least 16 planes) and never fewer than one
+// per 256 cells.
 inline int adjoint_blocks(const ic_params &p) {
     const long cells = ((long)p.nx * p.ny * p.nz + 255) / 256;
     const long tiles = (long)((p.nx + 31) / 32) * ((p.ny + 7) / 8) * ((p.nz + 15) / 16);
