@@ -227,6 +227,55 @@ def run_adjoint(prec, steps, warmup):
     return out
 
 
+def run_force_precision(steps):
+    """The paper-scale configuration with kT = 0 (256^3, 10^4 tethered
+    particles of split contrast, standing wave of amplitude 1e-2): FP32
+    (fields as deviations from rho0, FP64 particles and accumulators) against
+    all-FP64, the spring-force estimator of the radiation force averaged over
+    the last 7 whole drive periods of `steps` steps, and the FP32 speed-up."""
+    import torch
+
+    from paper_1307_0702_amd import ic
+    from paper_1307_0702_amd.ic import Simulation
+
+    w = make_workload("paper-scale-256")
+    fl, p = w.fluid, w.particles
+    fl.kT = 0.0
+    nT = w.period_steps
+    navg = 7 * nT
+    nwarm = max(steps - navg, 0)
+    eps = np.array([ic.ic_eps_from_kappa_ratio(fl.cf, r) for r in p.kappa_ratio])
+    out = {}
+    for prec in ("fp64", "fp32"):
+        sim = Simulation(fl, prec=prec, max_particles=p.n)
+        sim.set_state(w.drho, w.g)
+        sim.set_particles(p.q, p.me, eps, ks=p.ks, qeq=p.qeq, fext=p.fext)
+        sim.set_forcing([m.as_dict() for m in w.modes])
+        log(f"[bench] force precision {prec}: {nwarm} + {navg} steps")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(nwarm)
+        sim.avg_force(reset=True)
+        sim.step(navg)
+        f, _, ns = sim.avg_force(reset=True)
+        torch.cuda.synchronize()
+        out[prec] = (f, (time.perf_counter() - t0) / (nwarm + navg), ns)
+        del sim
+        torch.cuda.empty_cache()
+    f64, t64, _ = out["fp64"]
+    f32, t32, ns = out["fp32"]
+    rel_max = float(np.max(np.abs(f32 - f64)) / np.max(np.abs(f64)))
+    rel_rms = float(np.sqrt(np.mean((f32 - f64) ** 2) / np.mean(f64 ** 2)))
+    return dict(metric="FP32 speed-up over FP64 at the averaged radiation force error",
+                value=t64 / t32, unit="x", n_gpus=1, steps=nwarm + navg, warmup=0,
+                ms_per_step=t32 * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="f32", data="synthetic",
+                config=dict(workload="paper-scale-256-kT0", grid=[fl.nx, fl.ny, fl.nz],
+                            particles=p.n, kT=0.0, averaged_steps=ns, period_steps=nT),
+                fp64_ms_per_step=t64 * 1e3, force_rel_err_max=rel_max, force_rel_err_rms=rel_rms,
+                mean_abs_force_fp64=float(np.mean(np.abs(f64))))
+
+
 def measured_traffic(prec):
     """HBM bytes per stage launch from the committed counter summary, or None
     when the summary is missing or was taken on another kernel source."""
@@ -415,6 +464,9 @@ def main():
     if args.workload == "ensemble-64":
         print(json.dumps(run_ensemble("fp32" if args.prec == "both" else args.prec, args.steps,
                                       args.warmup)), flush=True)
+        return
+    if args.workload == "force-precision-256":
+        print(json.dumps(run_force_precision(args.steps)), flush=True)
         return
     if args.workload == "adjoint-256":
         for prec in (["fp32", "fp64"] if args.prec == "both" else [args.prec]):
