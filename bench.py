@@ -285,6 +285,67 @@ def run_force_precision(steps):
                 mean_abs_force_fp64=float(np.mean(np.abs(f64))))
 
 
+def run_gibbs_boltzmann(steps, warmup):
+    """Free dipolar particles in a thermal standing wave (32^3, kT = 1e-3):
+    the distribution of their phase 2 k xi against the Boltzmann
+    distribution in the acoustic potential (8 bins), and <cos 2 k xi>."""
+    import math
+
+    from scipy.special import i0, i1
+
+    from paper_1307_0702_amd import ic
+    from paper_1307_0702_amd import workloads as W
+    from paper_1307_0702_amd.ic import Simulation
+
+    V = 8.0
+    w = W.gibbs_boltzmann_32()
+    fl, mode, p = w.fluid, w.modes[0], w.particles
+    sim = Simulation(fl, prec="fp64", max_particles=p.n)
+    sim.set_state(w.drho, w.g)
+    eps = np.array([ic.ic_eps_from_kappa_ratio(fl.cf, r) for r in p.kappa_ratio])
+    sim.set_particles(p.q, p.me, eps, ks=p.ks, qeq=p.qeq)
+    sim.set_forcing([mode.as_dict()])
+    k = 2 * math.pi * mode.m / (fl.nx * fl.h)
+    t0 = time.perf_counter()
+    sim.step(warmup)
+    ph = []
+    every = 200
+    for _ in range(steps // every):
+        sim.step(every)
+        q, _ = sim.get_particles()
+        ph.append((2 * k * (q[:, 0] - mode.x0)) % (2 * math.pi))
+    wall = time.perf_counter() - t0
+    # amplitude of the driven density mode over one period
+    x = np.arange(fl.nx) * fl.h
+    c = np.cos(k * (x - mode.x0))
+    a2 = []
+    for _ in range(w.period_steps):
+        sim.step(1)
+        d, _ = sim.get_state()
+        a2.append((2.0 / fl.nx * np.sum(d.mean(axis=(0, 1)) * c)) ** 2)
+    a = math.sqrt(2.0 * np.mean(a2))
+    ph = np.array(ph)
+    f2 = 2 * w.particles.me[0] / (2 * w.particles.me[0] + 3 * fl.rho0 * V)
+    u0 = V * (fl.cf ** 2 * a) ** 2 * (1.5 * f2) / (8 * fl.rho0 * fl.cf ** 2) / fl.kT
+    per = np.cos(ph).mean(axis=0)
+    hist, edges = np.histogram(ph.ravel(), bins=8, range=(0, 2 * math.pi), density=True)
+    mid = 0.5 * (edges[1:] + edges[:-1])
+    # bin averages of exp(-u0 cos) / (2 pi I0(u0))
+    fine = np.linspace(0, 2 * math.pi, 8 * 64, endpoint=False) + math.pi / (8 * 64)
+    boltz = (np.exp(-u0 * np.cos(fine)) / (2 * math.pi * i0(u0))).reshape(8, 64).mean(axis=1)
+    return dict(metric="Gibbs-Boltzmann position distribution in a standing wave",
+                value=float(per.mean()), unit="<cos 2k xi>", n_gpus=1, steps=steps, warmup=warmup,
+                ms_per_step=wall * 1e3 / (steps + warmup), higher_is_better=False, scaling="weak",
+                vs_baseline=None, dtype="f64", data="synthetic",
+                config=dict(workload=w.name, grid=[fl.nx, fl.ny, fl.nz], particles=w.particles.n,
+                            kT=fl.kT, eta=fl.eta),
+                std_error=float(per.std() / math.sqrt(len(per))),
+                boltzmann=float(-i1(u0) / i0(u0)), u0_over_kT=float(u0), amplitude=float(a),
+                pdf_measured=[round(float(x), 4) for x in hist],
+                pdf_boltzmann=[round(float(x), 4) for x in boltz],
+                pdf_bin_centres=[round(float(x), 4) for x in mid])
+
+
 def measured_traffic(prec):
     """HBM bytes per stage launch from the committed counter summary, or None
     when the summary is missing or was taken on another kernel source."""
@@ -477,6 +538,9 @@ def main():
     if args.workload == "ensemble-64":
         print(json.dumps(run_ensemble("fp32" if args.prec == "both" else args.prec, args.steps,
                                       args.warmup)), flush=True)
+        return
+    if args.workload == "gibbs-boltzmann":
+        print(json.dumps(run_gibbs_boltzmann(args.steps, args.warmup)), flush=True)
         return
     if args.workload == "force-precision-256":
         print(json.dumps(run_force_precision(args.steps)), flush=True)

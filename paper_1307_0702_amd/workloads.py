@@ -268,6 +268,28 @@ def paper_scale_256(n=10000, seed=3):
     return Workload("paper-scale-256", fl, p, [mode], drho, g, nT)
 
 
+def gibbs_boltzmann_32(n_side=3, drho_amp=0.1, kT=1e-3, seed=5):
+    """32^3 in the paper's low-viscosity regime (eta = zeta = 0.0125), kT = 1e-3,
+    a resonant standing wave along x (drive amplitude for drho_amp without
+    particles; the free particles damp it to about a third), and
+    n_side x n_side free particles with m_p = 2 rho0 V, kappa_p = kappa_f
+    (Gor'kov contrast f2 = 0.4) on a lattice in y, z, at x drawn uniformly:
+    they collect around the pressure nodes as their Boltzmann distribution
+    in the acoustic potential says."""
+    fl = Fluid(32, 32, 32, kT=kT, seed=seed, eta=0.0125, zeta=0.0125)
+    mode, nT = modal_drive(fl, drho_amp)
+    drho, g = standing_wave_fields(fl, drho_amp, omega=mode.omega)
+    rng = np.random.default_rng(seed)
+    L = fl.nx * fl.h
+    yz = np.array([[(i + 0.5) * L / n_side, (j + 0.5) * L / n_side]
+                   for i in range(n_side) for j in range(n_side)])
+    n = len(yz)
+    q = np.column_stack([rng.uniform(0, L, n), yz])
+    V = 8.0 * fl.h ** 3
+    p = Particles(q=q, me=np.full(n, V), kappa_ratio=np.ones(n), ks=np.zeros(n), qeq=q.copy())
+    return Workload("gibbs-boltzmann-32", fl, p, [mode], drho, g, nT)
+
+
 def ensemble(n=64, seed=4000, sizes=(32, 48, 64), max_particles=50, kT=1e-3):
     """n independent thermal replicas: grid edge drawn from `sizes`, 1 to
     max_particles free particles with m_p/(rho0 V) ~ U[0.5, 2] and

@@ -296,3 +296,42 @@ def test_secondary_force_between_compressible_particles():
     r = f25[0, 2] / t25
     assert 1.5 < r < 3.5, r
 
+
+def gibbs_boltzmann(nwarm, nrun, every=200):
+    """Free dipolar particles in a thermal standing wave: the time average of
+    cos(2 k xi) (xi = x - x0 from the pressure antinode) against the
+    Boltzmann average in the acoustic potential U = U0 cos(2 k xi) + const,
+    U0 = V p_a^2 (f1 + 3/2 f2) / (8 rho0 c_f^2) (Sec. V, Eq. (1) integrated;
+    Sec. VI), <cos> = -I1(U0/kT) / I0(U0/kT).  Returns (measured, its
+    standard error over particles, Boltzmann value, U0/kT)."""
+    from scipy.special import i0, i1
+    w = W.gibbs_boltzmann_32()
+    fl, mode = w.fluid, w.modes[0]
+    sim = _sim(w, "fp64")
+    k = 2 * math.pi * mode.m / (fl.nx * fl.h)
+    sim.step(nwarm)
+    cs = []
+    for _ in range(nrun // every):
+        sim.step(every)
+        q, _ = sim.get_particles()
+        cs.append(np.cos(2 * k * (q[:, 0] - mode.x0)))
+    a = _amplitude(sim, w, w.period_steps)
+    cs = np.array(cs)
+    f2 = 2 * w.particles.me[0] / (2 * w.particles.me[0] + 3 * fl.rho0 * V)
+    u0 = V * (fl.cf ** 2 * a) ** 2 * (1.5 * f2) / (8 * fl.rho0 * fl.cf ** 2) / fl.kT
+    per = cs.mean(axis=0)
+    return float(per.mean()), float(per.std() / math.sqrt(len(per))), float(-i1(u0) / i0(u0)), u0
+
+
+def test_gibbs_boltzmann_position_distribution():
+    # Particles start spread uniformly along the wave and collect around the
+    # pressure nodes; the measured average (-0.339 +- 0.043 over 6e5 steps,
+    # U0/kT = 0.75) matches the Boltzmann value (-0.350).  The shorter run
+    # here is checked to three standard errors, and against the uniform
+    # distribution's 0.
+    m, se, th, u0 = gibbs_boltzmann(50000, 300000)
+    print(f"  <cos 2k xi> {m:.4f} +- {se:.4f}, Boltzmann {th:.4f}, U0/kT {u0:.3f}", flush=True)
+    assert 0.4 < u0 < 1.5
+    assert abs(m - th) < 3 * max(se, 0.03)
+    assert m < -0.1                      # well away from a uniform spread
+
