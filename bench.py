@@ -80,6 +80,8 @@ def make_workload(name):
         return W.thermal_128()
     if name == "standing-wave-32":
         return W.standing_wave_32()
+    if name == "adjoint-64":
+        return W.adjoint_64()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -231,6 +233,113 @@ def run_adjoint(prec, steps, warmup):
                config=dict(workload="adjoint-256", grid=[fl.nx, fl.ny, fl.nz], particles=0, kT=0.0),
                forward_ms_per_step=fwd, adjoint_over_forward=rev / fwd,
                finite=bool(torch.isfinite(lam).all()))
+    del adj, sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_adjoint_particles(prec, periods, fd_check):
+    """Reverse mode with particles: 64^3, kT = 0, 16 tethered particles, four
+    resonant drives along x.  L = the x-component of the spring-force
+    estimator <-F_tether> averaged over the particles and over `periods`
+    periods of the m = 1 drive; its gradient with respect to the four drive
+    amplitudes, m_p and kappa_p/kappa_f of every particle comes from a
+    checkpointed reversal (checkpoint every 64 steps).  Reports the cost of
+    one reversed step against one forward step, of the whole gradient
+    against the forward run, and (fd_check) directional derivatives against
+    central differences of the GPU forward run."""
+    import torch
+
+    from paper_1307_0702_amd import ic
+    from paper_1307_0702_amd.adjoint import Adjoint, rollout_particles
+    from paper_1307_0702_amd.ic import Simulation
+
+    w = make_workload("adjoint-64")
+    fl, p = w.fluid, w.particles
+    nsteps = periods * w.period_steps
+    md = [m.as_dict() for m in w.modes]
+    sim = Simulation(fl, prec=prec, max_particles=p.n)
+    kr = np.asarray(p.kappa_ratio, dtype=np.float64)
+    eps = np.array([ic.ic_eps_from_kappa_ratio(fl.cf, r) for r in kr])
+    sim.set_particles(p.q, p.me, eps, ks=p.ks, qeq=p.qeq, fext=p.fext)
+    sim.set_forcing(md)
+    adj = Adjoint(sim)
+    dev = sim.device
+    q0 = torch.empty((p.n, 3), dtype=torch.float64, device=dev)
+    u0 = torch.empty_like(q0)
+    ic.ic_copy_particles(sim.ctx, q0, u0)
+    U0 = torch.zeros((4,) + sim.shape, dtype=sim.dtype, device=dev)
+
+    # one step each way, device-timed back to back
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(k):
+            fn(i)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / k
+
+    U, qs, us = adj.snapshot()
+    lam = torch.randn_like(sim.U)
+    lq = torch.randn((p.n, 3), dtype=torch.float64, device=dev)
+    lu = torch.randn_like(lq)
+    lF = torch.randn_like(lq)
+    timed(lambda i: sim.step(1), 50)
+    fwd = timed(lambda i: sim.step(1), 500)
+    timed(lambda i: adj.step(i, U, lam, qs, us, lq, lu, lF), 20)
+    rev = timed(lambda i: adj.step(i, U, lam, qs, us, lq, lu, lF), 200)
+
+    amps = torch.tensor([m["amp"] for m in md], dtype=torch.float64)
+    me = torch.tensor(p.me, dtype=torch.float64)
+    epst = torch.tensor(eps, dtype=torch.float64)
+    fixed = dict(ks=p.ks, qeq=p.qeq, fext=p.fext)
+
+    def loss(amps_, me_, eps_):
+        _, _, _, F = rollout_particles(adj, U0, q0, u0, amps_, me_, eps_, md, 0, nsteps, 64, **fixed)
+        return -F[:, 0].mean()     # mean x-component of -F_tether (f_ext = 0)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.no_grad():
+        L0 = float(loss(amps, me, epst))
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    xs = [amps.clone().requires_grad_(True), me.clone().requires_grad_(True),
+          epst.clone().requires_grad_(True)]
+    t0 = time.perf_counter()
+    L = loss(*xs)
+    L.backward()
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    dA, dme, deps = (x.grad.numpy() for x in xs)
+    dkr = -fl.cf ** 2 / kr ** 2 * deps          # eps = cf^2 (1/r - 1)
+    out = dict(metric="adjoint particle-steps/s", value=p.n * nsteps / t_grad, unit="particle-steps/s",
+               n_gpus=1, steps=nsteps, warmup=0, ms_per_step=t_grad * 1e3 / nsteps,
+               higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f32" if prec == "fp32" else "f64", data="synthetic",
+               config=dict(workload="adjoint-64", grid=[fl.nx, fl.ny, fl.nz], particles=p.n, kT=0.0,
+                           drives=4, periods=periods, checkpoint_every=64),
+               forward_step_ms=fwd, adjoint_step_ms=rev, adjoint_step_over_forward_step=rev / fwd,
+               forward_run_s=t_fwd, gradient_run_s=t_grad, gradient_over_forward_run=t_grad / t_fwd,
+               loss=L0, dL_damp=dA.tolist(), dL_dmp=dme.tolist(), dL_dkappa_ratio=dkr.tolist())
+    if fd_check:
+        rng = np.random.default_rng(7)
+        fd = {}
+        # steps large enough that 2 h dL stands well above the rounding of
+        # positions accumulated over the run (L is quadratic in the drive
+        # amplitudes, so their central difference has no curvature error)
+        for name, i, h in (("amp", 0, 1e-2 * float(amps.abs().max())), ("m_p", 1, 1e-3),
+                           ("eps", 2, 1e-3)):
+            base = [amps, me, epst]
+            d = torch.as_tensor(rng.standard_normal(tuple(base[i].shape)), dtype=torch.float64)
+            ap = [b if j != i else b + h * d for j, b in enumerate(base)]
+            am = [b if j != i else b - h * d for j, b in enumerate(base)]
+            with torch.no_grad():
+                f = (float(loss(*ap)) - float(loss(*am))) / (2 * h)
+            an = float((xs[i].grad * d).sum())
+            fd[name] = dict(fd=f, adjoint=an, rel=abs(f - an) / max(abs(f), 1e-300))
+            log(f"[bench] adjoint-64 {prec} {name}: fd {f:.10e} adjoint {an:.10e}")
+        out["central_differences"] = fd
     del adj, sim
     torch.cuda.empty_cache()
     return out
@@ -513,6 +622,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="paper-scale-256")
     ap.add_argument("--prec", choices=["fp32", "fp64", "both"], default="both")
+    ap.add_argument("--periods", type=int, default=20,
+                    help="adjoint-64: drive periods the loss averages over")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--stats-summary", metavar="CSV")
@@ -544,6 +655,11 @@ def main():
         return
     if args.workload == "force-precision-256":
         print(json.dumps(run_force_precision(args.steps)), flush=True)
+        return
+    if args.workload == "adjoint-64":
+        for prec in (["fp32", "fp64"] if args.prec == "both" else [args.prec]):
+            print(json.dumps(run_adjoint_particles(prec, args.periods, fd_check=prec == "fp64")),
+                  flush=True)
         return
     if args.workload == "adjoint-256":
         for prec in (["fp32", "fp64"] if args.prec == "both" else [args.prec]):

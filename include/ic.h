@@ -218,7 +218,8 @@ int ic_graph_destroy(ic_graph *graph);
  * The step is the three SSP-RK3 stages of App. A with the conservative
  * staggered flux; its transpose runs the stages backwards.
  * ic_adjoint_workspace_size: bytes of the extra device workspace (16 fields
- * of the context precision plus IC_MAX_MODES doubles per 256 cells).
+ * of the context precision, IC_MAX_MODES doubles per 256 cells and 18
+ * doubles per particle of max_particles).
  * ic_bind_adjoint: binds it (caller-owned, 256-byte aligned) and zeroes the
  * drive-gradient accumulator.  Synchronising.
  * ic_adjoint_step: for step n taken from the state U^n = (drho, gx, gy, gz)
@@ -238,6 +239,47 @@ int ic_bind_adjoint(ic_ctx *ctx, void *workspace, size_t bytes);
 int ic_adjoint_step(ic_ctx *ctx, int64_t n, const void *drho, const void *gx, const void *gy,
                     const void *gz, void *ldrho, void *lgx, void *lgy, void *lgz);
 int ic_adjoint_drive(ic_ctx *ctx, double *grad, int32_t reset);
+
+/* Reverse mode of the whole deterministic IC step with particles (kT = 0):
+ * the seven substeps of App. A reversed (substep 7 first, the RK stages from
+ * the third to the first), including the particle pressure
+ * S(eps_pf V J rho) of Sec. III, the spread tether force, the no-slip
+ * impulse of Sec. IV B and the dependence of every kernel weight on the
+ * particle position through phi' (phi is C^1, App. A).
+ * ic_adjoint_step_particles: as ic_adjoint_step for U^n and the field
+ * adjoints, plus device arrays ([n][3] doubles, n = the context's particle
+ * count): q, u = the particle state at step n (as ic_copy_particles returns
+ * it, positions inside the box; read only); lq, lu = dL/dq^{n+1}, dL/du^{n+1}
+ * on entry, dL/dq^n, dL/du^n on return; lF = dL/dF^{n+1/2} for a loss on
+ * this step's force F = -k_s minimg(q^{n+1/2} - q_eq) + f_ext (the
+ * radiation-force estimator of Sec. VI is its mean), or NULL.  Adds this
+ * step's dL/dm_e, dL/deps_pf and dL/dk_s to per-particle accumulators and
+ * dL/dA_m to the drive accumulator.  The particle parameters (m_e, eps_pf,
+ * k_s, q_eq, f_ext) are the context's.  Scatters into the field adjoints
+ * use atomic adds: results are repeatable to rounding, not bitwise.
+ * Asynchronous; uses the forward workspace, like ic_adjoint_step.  With no
+ * particles it is ic_adjoint_step.  IC_E_STATE if the adjoint workspace is
+ * unbound or kT != 0; IC_E_ARG for NULL fields, NULL particle arrays while
+ * particles are set, or n < 0.
+ * ic_adjoint_particle_grad: copies the accumulated dL/dm_e, dL/deps_pf and
+ * dL/dk_s (host, double[n] each, any may be NULL); reset != 0 zeroes them.
+ * dL/dm_p = dL/dm_e (m_p = m_e + rho0 V); for kappa_p/kappa_f = r,
+ * dL/dr = -cf^2 / r^2 dL/deps_pf (Eq. part_svel).  Synchronising.
+ * ic_copy_particles / ic_load_particles: device-to-device copy of the
+ * current positions and velocities out of / into the context ([n][3]
+ * doubles, either may be NULL), for checkpoints of a reversed trajectory.
+ * ic_copy_particles is asynchronous.  ic_load_particles checks the
+ * positions on the host and wraps them into the box (IC_E_ARG if one is not
+ * finite; synchronising).  A non-finite position handed to
+ * ic_adjoint_step_particles is replaced by 0 and reported as IC_E_ARG by the
+ * next synchronising call. */
+int ic_adjoint_step_particles(ic_ctx *ctx, int64_t n, const void *drho, const void *gx,
+                              const void *gy, const void *gz, const double *q, const double *u,
+                              void *ldrho, void *lgx, void *lgy, void *lgz, double *lq, double *lu,
+                              const double *lF);
+int ic_adjoint_particle_grad(ic_ctx *ctx, double *dme, double *deps, double *dks, int32_t reset);
+int ic_copy_particles(ic_ctx *ctx, double *q, double *u);
+int ic_load_particles(ic_ctx *ctx, const double *q, const double *u);
 
 const char *ic_strerror(int code);
 const char *ic_last_error(const ic_ctx *ctx);

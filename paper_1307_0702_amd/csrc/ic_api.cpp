@@ -105,6 +105,12 @@ static size_t adj_layout(const ic_params &p, char *base, AdjWorkspace *aw) {
     for (int i = 0; i < 3; ++i) w.murf[i] = take(ncell * esz);
     w.mur = take(ncell * esz);
     w.partial = (double *)take((size_t)IC_MAX_MODES * adjoint_blocks(p) * sizeof(double));
+    const size_t N = (size_t)(p.max_particles > 0 ? p.max_particles : 0);
+    auto d3 = [&]() { return (double *)take(3 * N * sizeof(double)); };
+    auto d1 = [&]() { return (double *)take(N * sizeof(double)); };
+    w.plqh = d3(); w.plF = d3(); w.plVt = d3(); w.plmf = d3();
+    w.pdme = d1(); w.pdeps = d1(); w.pdks = d1();
+    w.pq = d3();
     if (aw) *aw = w;
     return off;
 }
@@ -183,17 +189,20 @@ int check_bound(ic_ctx *c) {
     return IC_OK;
 }
 
+// Device flags: [0] a step found m_e + m_f <= 0, [1] a reversed step got a
+// non-finite particle position.
 int take_flag(ic_ctx *c) {
-    int32_t flag = 0;
-    hipError_t e = hipMemcpyAsync(&flag, c->ws.flag, sizeof(flag), hipMemcpyDeviceToHost, c->stream);
+    int32_t flag[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(flag, c->ws.flag, sizeof(flag), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "flag readback");
-    if (flag) {
-        int32_t zero = 0;
-        e = hipMemcpyAsync(c->ws.flag, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream);
+    if (flag[0] || flag[1]) {
+        const int32_t zero[2] = {0, 0};
+        e = hipMemcpyAsync(c->ws.flag, zero, sizeof(zero), hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "flag reset");
-        return fail(c, IC_E_MASS, "a step found m_e + m_f <= 0");
+        if (flag[0]) return fail(c, IC_E_MASS, "a step found m_e + m_f <= 0");
+        return fail(c, IC_E_ARG, "a reversed step got a non-finite particle position");
     }
     return IC_OK;
 }
@@ -608,6 +617,9 @@ int ic_bind_adjoint(ic_ctx *c, void *workspace, size_t bytes) {
     carve_adjoint(c->p, (char *)workspace, c->adj);
     hipError_t e = hipMemsetAsync(c->adj.partial, 0,
                                   (size_t)IC_MAX_MODES * adjoint_blocks(c->p) * sizeof(double), c->stream);
+    const size_t pb = (size_t)c->p.max_particles * sizeof(double);
+    for (double *g : {c->adj.pdme, c->adj.pdeps, c->adj.pdks})
+        if (e == hipSuccess && pb) e = hipMemsetAsync(g, 0, pb, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "bind adjoint");
     c->adj_bound = true;
@@ -626,8 +638,87 @@ int ic_adjoint_step(ic_ctx *c, int64_t n, const void *drho, const void *gx, cons
         return fail(c, IC_E_ARG, "NULL field");
     const void *const Un[4] = {drho, gx, gy, gz};
     void *const lam[4] = {ldrho, lgx, lgy, lgz};
-    hipError_t e = launch_adjoint_step(c, n, Un, lam);
+    hipError_t e = launch_adjoint_step(c, n, Un, lam, nullptr);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint step");
+    return IC_OK;
+}
+
+int ic_adjoint_step_particles(ic_ctx *c, int64_t n, const void *drho, const void *gx,
+                              const void *gy, const void *gz, const double *q, const double *u,
+                              void *ldrho, void *lgx, void *lgy, void *lgz, double *lq, double *lu,
+                              const double *lF) {
+    int rc = check_bound(c);
+    if (rc != IC_OK) return rc;
+    if (!c->adj_bound) return fail(c, IC_E_STATE, "adjoint workspace not bound");
+    if (c->p.kT != 0.0) return fail(c, IC_E_STATE, "adjoint needs kT = 0");
+    if (n < 0) return fail(c, IC_E_ARG, "step must be >= 0");
+    if (!drho || !gx || !gy || !gz || !ldrho || !lgx || !lgy || !lgz)
+        return fail(c, IC_E_ARG, "NULL field");
+    if (c->np > 0 && (!q || !u || !lq || !lu)) return fail(c, IC_E_ARG, "NULL particle array");
+    const void *const Un[4] = {drho, gx, gy, gz};
+    void *const lam[4] = {ldrho, lgx, lgy, lgz};
+    const AdjParticles pp{q, u, lq, lu, lF};
+    hipError_t e = launch_adjoint_step(c, n, Un, lam, &pp);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint step");
+    return IC_OK;
+}
+
+int ic_adjoint_particle_grad(ic_ctx *c, double *dme, double *deps, double *dks, int32_t reset) {
+    if (!c) return IC_E_ARG;
+    if (!c->adj_bound) return fail(c, IC_E_STATE, "adjoint workspace not bound");
+    const size_t b = (size_t)c->np * sizeof(double);
+    hipError_t e = hipSuccess;
+    double *host[3] = {dme, deps, dks};
+    double *dev[3] = {c->adj.pdme, c->adj.pdeps, c->adj.pdks};
+    for (int k = 0; k < 3; ++k)
+        if (e == hipSuccess && host[k] && b)
+            e = hipMemcpyAsync(host[k], dev[k], b, hipMemcpyDeviceToHost, c->stream);
+    if (reset) {
+        const size_t pb = (size_t)c->p.max_particles * sizeof(double);
+        for (int k = 0; k < 3; ++k)
+            if (e == hipSuccess && pb) e = hipMemsetAsync(dev[k], 0, pb, c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint particle gradients");
+    return take_flag(c);
+}
+
+int ic_copy_particles(ic_ctx *c, double *q, double *u) {
+    int rc = check_bound(c);
+    if (rc != IC_OK) return rc;
+    const size_t b3 = 3 * (size_t)c->np * sizeof(double);
+    hipError_t e = hipSuccess;
+    if (q && b3) e = hipMemcpyAsync(q, c->ws.q, b3, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && u && b3) e = hipMemcpyAsync(u, c->ws.u, b3, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "copy_particles");
+    return IC_OK;
+}
+
+int ic_load_particles(ic_ctx *c, const double *q, const double *u) {
+    int rc = check_bound(c);
+    if (rc != IC_OK) return rc;
+    const size_t n3 = 3 * (size_t)c->np, b3 = n3 * sizeof(double);
+    hipError_t e = hipSuccess;
+    if (q && b3) {
+        // positions index the grid: checked and wrapped on the host
+        std::vector<double> hq(n3);
+        e = hipMemcpyAsync(hq.data(), q, b3, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "load_particles");
+        const double L[3] = {c->p.nx * c->p.h, c->p.ny * c->p.h, c->p.nz * c->p.h};
+        for (size_t i = 0; i < n3; ++i) {
+            if (!isfinite(hq[i])) return fail(c, IC_E_ARG, "non-finite position");
+            const double Li = L[i % 3];
+            double x = fmod(hq[i], Li);
+            if (x < 0) x += Li;
+            if (x >= Li) x -= Li;
+            hq[i] = x;
+        }
+        e = hipMemcpyAsync(c->ws.q, hq.data(), b3, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    if (e == hipSuccess && u && b3) e = hipMemcpyAsync(c->ws.u, u, b3, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "load_particles");
     return IC_OK;
 }
 

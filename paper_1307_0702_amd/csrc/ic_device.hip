@@ -1755,6 +1755,350 @@ __global__ __launch_bounds__(256) void k_adj_rho(const AdjArgs<T> a) {
     adj_combine(a, 0, j, a.lam[0][j], mu);
 }
 
+// ---------------------------------------------------------------------------
+// Reverse mode of the particle coupling (App. A substeps 1-2 and 4-7, and the
+// particle pressure and spread force inside each RK stage increment), one
+// 64-lane wave per particle.  Gathers use the kernel weights and their
+// position gradients (phi is C^1, so phi' exists everywhere); scatters into
+// the adjoint fields are atomic adds, so the rounding order of the adjoint
+// (not its value) can differ from run to run.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double dphi3(double r) {
+    const double a = fabs(r);
+    if (a <= 0.5) return -r / sqrt(1.0 - 3.0 * r * r);
+    if (a <= 1.5) {
+        const double s = 1.0 - a;
+        const double v = 0.5 + s / (2.0 * sqrt(1.0 - 3.0 * s * s));
+        return r > 0.0 ? -v : v;
+    }
+    return 0.0;
+}
+
+// Point pt (0..26, x fastest) of the kernel of location kind (0 cell, 1 + a
+// face a) at q in the box: element index, grid coordinates, weight w =
+// prod phi, its gradient dw/dq and, for a face, the index of the second
+// cell of the face density (the next cell along a).
+struct KPoint {
+    size_t i, nb;
+    int c[3];
+    double w, dw[3];
+};
+
+__device__ __forceinline__ KPoint kpoint(const Grid &G, const double q[3], int kind, int pt) {
+    const int n[3] = {G.nx, G.ny, G.nz};
+    const int d[3] = {pt % 3, (pt / 3) % 3, pt / 9};
+    double ph[3], dph[3];
+    KPoint k;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const double x = q[ax] * G.inv_h - (kind == ax + 1 ? 0.5 : 0.0);
+        const double nearest = floor(x + 0.5);
+        const double r = x - (nearest - 1.0 + d[ax]);
+        ph[ax] = phi3(r);
+        dph[ax] = dphi3(r) * G.inv_h;
+        k.c[ax] = wrap((int)nearest - 1 + d[ax], n[ax]);
+    }
+    k.w = ph[0] * ph[1] * ph[2];
+    k.dw[0] = dph[0] * ph[1] * ph[2];
+    k.dw[1] = ph[0] * dph[1] * ph[2];
+    k.dw[2] = ph[0] * ph[1] * dph[2];
+    k.i = ((size_t)k.c[2] * G.ny + k.c[1]) * G.nx + k.c[0];
+    k.nb = k.i;
+    if (kind > 0) {
+        int c2[3] = {k.c[0], k.c[1], k.c[2]};
+        const int a = kind - 1;
+        c2[a] = c2[a] + 1 == n[a] ? 0 : c2[a] + 1;
+        k.nb = ((size_t)c2[2] * G.ny + c2[1]) * G.nx + c2[0];
+    }
+    return k;
+}
+
+template <typename T>
+struct AdjPartArgs {
+    Grid G;
+    int np;
+    double dt, V, inv_h3, L[3], cs;   // cs: weight of the reversed RK stage
+    const T *Un[4];     // state before the step
+    const T *U3[4];     // third stage output before the no-slip correction
+    const T *gnew[3];   // momentum after the correction
+    const T *Us;        // density of the reversed stage's input
+    const T *lin[4];    // adjoint of the reversed stage's output
+    T *lam[4];          // adjoint fields receiving the scatters
+    const double *q, *u;          // particle state before the step
+    double *lq, *lu;              // in: dL/d(q, u) after the step; out: before
+    const double *lF;             // dL/dF^{n+1/2} of this step, or nullptr
+    const double *me, *eps, *ks, *qeq, *qh, *F, *un, *du, *mf;
+    double *lqh, *lFt, *lVt, *lmf, *dme, *deps, *dks;
+};
+
+// Positions of a reversed step wrapped into the box (they index the grid); a
+// non-finite component becomes 0 and raises flag[1].
+__global__ __launch_bounds__(256) void k_adjp_positions(int np, const double *q, double *out,
+                                                        double L0, double L1, double L2,
+                                                        int32_t *flag) {
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= 3 * np) return;
+    const int ax = i % 3;
+    const double L = ax == 0 ? L0 : (ax == 1 ? L1 : L2);
+    double x = q[i];
+    if (!isfinite(x)) {
+        x = 0.0;
+        flag[1] = 1;
+    }
+    out[i] = wrap_pos(x, L);
+}
+
+template <typename T>
+__device__ __forceinline__ void scatter_face_density(T *lr, const KPoint &k, double v) {
+    atomicAdd(lr + k.i, (T)(0.5 * v));
+    atomicAdd(lr + k.nb, (T)(0.5 * v));
+}
+
+// Substep 7 reversed: q^{n+1} = q^n + dt/2 J(v^{n+1} + v^n) at q^{n+1/2}.
+// Scatters the J v^{n+1} part into the adjoint of g^{n+1} and rho^{n+1};
+// starts the per-particle accumulators.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adjp_final(const AdjPartArgs<T> a) {
+    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (p >= a.np) return;
+    const int lane = threadIdx.x & 63;
+    const double qh[3] = {a.qh[3 * p], a.qh[3 * p + 1], a.qh[3 * p + 2]};
+    const double lJ[3] = {0.5 * a.dt * a.lq[3 * p], 0.5 * a.dt * a.lq[3 * p + 1],
+                          0.5 * a.dt * a.lq[3 * p + 2]};
+    double gq[3] = {0, 0, 0};
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const int item = lane + 64 * it;
+        if (item < 81) {
+            const int ax = item / 27;
+            const KPoint k = kpoint(a.G, qh, ax + 1, item % 27);
+            const double rf = a.G.rho0 + 0.5 * ((double)a.U3[0][k.i] + (double)a.U3[0][k.nb]);
+            const double gn = (double)a.gnew[ax][k.i];
+            atomicAdd(a.lam[1 + ax] + k.i, (T)(lJ[ax] * k.w / rf));
+            scatter_face_density(a.lam[0], k, -lJ[ax] * k.w * gn / (rf * rf));
+#pragma unroll
+            for (int b = 0; b < 3; ++b) gq[b] += lJ[ax] * k.dw[b] * (gn / rf);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) gq[b] = wave_sum(gq[b]);
+    if (lane < 3) {
+        a.lqh[3 * p + lane] = gq[lane];
+        a.lFt[3 * p + lane] = a.lF ? a.lF[3 * p + lane] : 0.0;
+    }
+}
+
+// Substeps 6 and 5 reversed, gather side: the no-slip correction
+// g^{n+1} = g~ + rho_face V S(u^{n+1} - V~) and the particle velocity
+// u^{n+1} = u^n + m_f/(m_e + m_f) (V~ - u^n).  Reads the complete adjoint of
+// g^{n+1}; keeps dL/dV~ and dL/dm_f for k_adjp_velocity.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adjp_noslip(const AdjPartArgs<T> a) {
+    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (p >= a.np) return;
+    const int lane = threadIdx.x & 63;
+    const double qh[3] = {a.qh[3 * p], a.qh[3 * p + 1], a.qh[3 * p + 2]};
+    const double du[3] = {a.du[3 * p], a.du[3 * p + 1], a.du[3 * p + 2]};   // V (u^{n+1} - V~)
+    double sd[3] = {0, 0, 0}, gq[3] = {0, 0, 0};
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const int item = lane + 64 * it;
+        if (item < 81) {
+            const int ax = item / 27;
+            const KPoint k = kpoint(a.G, qh, ax + 1, item % 27);
+            const double rf = a.G.rho0 + 0.5 * ((double)a.U3[0][k.i] + (double)a.U3[0][k.nb]);
+            const double lg = (double)a.lam[1 + ax][k.i];
+            sd[ax] += k.w * lg * rf;
+            scatter_face_density(a.lam[0], k, lg * k.w * du[ax] * a.inv_h3);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) gq[b] += du[ax] * a.inv_h3 * k.dw[b] * lg * rf;
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        sd[b] = wave_sum(sd[b]);
+        gq[b] = wave_sum(gq[b]);
+    }
+    const double me = a.me[p];
+    double dme = 0.0, lu_out[3], lVt[3], lmf[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const double ldu = a.V * a.inv_h3 * sd[ax];
+        const double un = a.un[3 * p + ax], mf = a.mf[3 * p + ax];
+        const double Vt = un - du[ax] / a.V;
+        const double lun = a.lu[3 * p + ax] + ldu;
+        const double mt = me + mf, c = mf / mt;
+        lu_out[ax] = lun * (1.0 - c);
+        lVt[ax] = c * lun - ldu;
+        const double lc = lun * (Vt - a.u[3 * p + ax]);
+        lmf[ax] = lc * me / (mt * mt);
+        dme -= lc * mf / (mt * mt);
+    }
+    if (lane < 3) {
+        a.lqh[3 * p + lane] += gq[lane];
+        a.lVt[3 * p + lane] = lVt[lane];
+        a.lmf[3 * p + lane] = lmf[lane];
+        a.lu[3 * p + lane] = lu_out[lane];
+    }
+    if (lane == 0) a.dme[p] += dme;
+}
+
+// Substeps 4-5 reversed, scatter side: V~ = J(g~ / rho_face) and
+// m_f = V J rho_face at q^{n+1/2}, into the adjoint of the third stage output.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adjp_velocity(const AdjPartArgs<T> a) {
+    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (p >= a.np) return;
+    const int lane = threadIdx.x & 63;
+    const double qh[3] = {a.qh[3 * p], a.qh[3 * p + 1], a.qh[3 * p + 2]};
+    const double lVt[3] = {a.lVt[3 * p], a.lVt[3 * p + 1], a.lVt[3 * p + 2]};
+    const double lm[3] = {a.V * a.lmf[3 * p], a.V * a.lmf[3 * p + 1], a.V * a.lmf[3 * p + 2]};
+    double gq[3] = {0, 0, 0};
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const int item = lane + 64 * it;
+        if (item < 81) {
+            const int ax = item / 27;
+            const KPoint k = kpoint(a.G, qh, ax + 1, item % 27);
+            const double rf = a.G.rho0 + 0.5 * ((double)a.U3[0][k.i] + (double)a.U3[0][k.nb]);
+            const double g3 = (double)a.U3[1 + ax][k.i];
+            atomicAdd(a.lam[1 + ax] + k.i, (T)(lVt[ax] * k.w / rf));
+            scatter_face_density(a.lam[0], k, -lVt[ax] * k.w * g3 / (rf * rf) + lm[ax] * k.w);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) gq[b] += k.dw[b] * (lVt[ax] * (g3 / rf) + lm[ax] * rf);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) gq[b] = wave_sum(gq[b]);
+    if (lane < 3) a.lqh[3 * p + lane] += gq[lane];
+}
+
+// Particle terms of one reversed RK stage increment (weight cs): the stage
+// pressure S(eps V J rho_s) and the spread force dt S F, both at q^{n+1/2}.
+// mu_p (the adjoint of the cell pressure) is formed from the stage's output
+// adjoint; the density part is added to the stage's input adjoint (after
+// k_adj_rho wrote it).
+template <typename T>
+__global__ __launch_bounds__(256) void k_adjp_stage(const AdjPartArgs<T> a) {
+    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (p >= a.np) return;
+    const int lane = threadIdx.x & 63;
+    const double qh[3] = {a.qh[3 * p], a.qh[3 * p + 1], a.qh[3 * p + 2]};
+    const double F[3] = {a.F[3 * p], a.F[3 * p + 1], a.F[3 * p + 2]};
+    const double kdt = a.dt * a.G.inv_h;
+    const int n[3] = {a.G.nx, a.G.ny, a.G.nz};
+    const size_t stride[3] = {1, (size_t)a.G.nx, (size_t)a.G.nx * a.G.ny};
+    double sP = 0, sJ = 0, gP[3] = {0, 0, 0}, gJ[3] = {0, 0, 0};
+    double sF[3] = {0, 0, 0}, gF[3] = {0, 0, 0};
+    KPoint kc;
+    kc.w = 0.0;
+    kc.i = 0;
+    if (lane < 27) {
+        kc = kpoint(a.G, qh, 0, lane);
+        double mp = 0.0;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const size_t im = kc.c[ax] == 0 ? kc.i + (size_t)(n[ax] - 1) * stride[ax] : kc.i - stride[ax];
+            mp -= kdt * ((double)a.lin[1 + ax][im] - (double)a.lin[1 + ax][kc.i]);
+        }
+        const double r = (double)a.Us[kc.i];
+        sP = kc.w * mp;
+        sJ = kc.w * r;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            gP[b] = kc.dw[b] * mp;
+            gJ[b] = kc.dw[b] * r;
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const int item = lane + 64 * it;
+        if (item < 81) {
+            const int ax = item / 27;
+            const KPoint k = kpoint(a.G, qh, ax + 1, item % 27);
+            const double lg = (double)a.lin[1 + ax][k.i];
+            sF[ax] += k.w * lg;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) gF[b] += F[ax] * k.dw[b] * lg;
+        }
+    }
+    sP = wave_sum(sP);
+    sJ = wave_sum(sJ);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        gP[b] = wave_sum(gP[b]);
+        gJ[b] = wave_sum(gJ[b]);
+        sF[b] = wave_sum(sF[b]);
+        gF[b] = wave_sum(gF[b]);
+    }
+    const double P = sP * a.inv_h3, eps = a.eps[p];
+    if (lane < 27) atomicAdd(a.lam[0] + kc.i, (T)(a.cs * eps * a.V * kc.w * P));
+    if (lane < 3) {
+        const int b = lane;
+        a.lqh[3 * p + b] += a.cs * (eps * a.V * (sJ * gP[b] * a.inv_h3 + P * gJ[b]) +
+                                    a.dt * a.inv_h3 * gF[b]);
+        a.lFt[3 * p + b] += a.cs * a.dt * a.inv_h3 * sF[b];
+    }
+    if (lane == 0) a.deps[p] += a.cs * a.V * sJ * P;
+}
+
+// Substeps 2 and 1 reversed, after the stages: F = -k_s minimg(q^{n+1/2} -
+// q_eq) + f_ext, J v^n at q^{n+1/2} (kept for substep 7) and q^{n+1/2} =
+// q^n + dt/2 J v^n at q^n; scatters into the adjoint of the state before the
+// step and writes dL/dq^n.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adjp_start(const AdjPartArgs<T> a) {
+    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (p >= a.np) return;
+    const int lane = threadIdx.x & 63;
+    double lqh[3], lv[3], pos[3];
+    double dks = 0.0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const double lF = a.lFt[3 * p + b];
+        pos[b] = a.qh[3 * p + b];
+        lqh[b] = a.lqh[3 * p + b] - a.ks[p] * lF;
+        dks -= lF * min_image(pos[b] - a.qeq[3 * p + b], a.L[b]);
+        lv[b] = 0.5 * a.dt * a.lq[3 * p + b];
+    }
+    double lq[3] = {a.lq[3 * p], a.lq[3 * p + 1], a.lq[3 * p + 2]};
+    // pass 0: J v^n at q^{n+1/2}; pass 1: J v^n at q^n
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+        double gq[3] = {0, 0, 0};
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+            const int item = lane + 64 * it;
+            if (item < 81) {
+                const int ax = item / 27;
+                const KPoint k = kpoint(a.G, pos, ax + 1, item % 27);
+                const double rf = a.G.rho0 + 0.5 * ((double)a.Un[0][k.i] + (double)a.Un[0][k.nb]);
+                const double g0 = (double)a.Un[1 + ax][k.i];
+                atomicAdd(a.lam[1 + ax] + k.i, (T)(lv[ax] * k.w / rf));
+                scatter_face_density(a.lam[0], k, -lv[ax] * k.w * g0 / (rf * rf));
+#pragma unroll
+                for (int b = 0; b < 3; ++b) gq[b] += lv[ax] * k.dw[b] * (g0 / rf);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b) gq[b] = wave_sum(gq[b]);
+        if (pass == 0) {
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                lqh[b] += gq[b];
+                lq[b] += lqh[b];
+                lv[b] = 0.5 * a.dt * lqh[b];
+                pos[b] = a.q[3 * p + b];
+            }
+        } else {
+#pragma unroll
+            for (int b = 0; b < 3; ++b) lq[b] += gq[b];
+        }
+    }
+    if (lane < 3) a.lq[3 * p + lane] = lq[lane];
+    if (lane == 0) a.dks[p] += dks;
+}
+
 // FP64 block partial sums of the four fields (deterministic order).
 template <typename T>
 __global__ __launch_bounds__(256) void k_sums(const T *f0, const T *f1, const T *f2, const T *f3,
@@ -2068,11 +2412,15 @@ hipError_t sums_impl(ic_ctx *c, double *host4) {
 
 }  // namespace
 
-// Reverse of one deterministic particle-free step (see k_adj_tile).  The
-// stage inputs U1, U2 of step n are recomputed from U^n with the forward
-// stage kernels into the workspace stage buffers.
+// Reverse of one deterministic step (see k_adj_tile and the k_adjp_*
+// kernels).  The stage inputs U1, U2 of step n are recomputed from U^n with
+// the forward stage kernels into the workspace stage buffers; with
+// particles, also the particle prologue at q^n, the third stage output
+// (into L1) and the no-slip-corrected momentum (into acc), which the
+// reversed substeps 4-7 read before the stage reversal overwrites them.
 template <typename T>
-hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *const lam[4]) {
+hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *const lam[4],
+                        const AdjParticles *pp) {
     const ic_params &p = c->p;
     hipStream_t s = c->stream;
     const Workspace &w = c->ws;
@@ -2081,6 +2429,29 @@ hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *con
     const unsigned nb = (unsigned)((ncell + 255) / 256);
     const unsigned nblk_all = (unsigned)(c->nblk[0] * c->nblk[1] * c->nblk[2]);
     const bool full = p.nx % TX == 0 && p.ny % TY == 0;
+    const int np = pp ? c->np : 0;
+    const dim3 sgrid(c->nblk[0], c->nblk[1], c->nblk[2]);
+    PartArgs<T> pa{};
+    if (np > 0) {
+        void *f[4] = {const_cast<void *>(Un[0]), const_cast<void *>(Un[1]),
+                      const_cast<void *>(Un[2]), const_cast<void *>(Un[3])};
+        pa = part_args<T>(c, f);
+        hipLaunchKernelGGL(k_adjp_positions, dim3(thread_blocks(3 * np)), dim3(256), 0, s, np, pp->q,
+                           aw.pq, p.nx * p.h, p.ny * p.h, p.nz * p.h, w.flag);
+        pa.q = aw.pq;
+        pa.u = const_cast<double *>(pp->u);
+    }
+    // particle terms of recomputed stage st, written into the stage output
+    auto stage_particles = [&](int st, void *const *dst) {
+        if (np == 0) return;
+        SparseArgs<T> sa = sparse_args<T>(c);
+        const double rb[3] = {1.0, 0.25, 2.0 / 3.0};
+        sa.b = rb[st];
+        sa.val = w.F;
+        sa.omega = w.omega;
+        for (int i = 0; i < 3; ++i) sa.fields[i] = (T *)dst[1 + i];
+        hipLaunchKernelGGL((k_sparse<T, SP_STAGE>), sgrid, dim3(SP_THREADS), 0, s, sa);
+    };
 
     // stage inputs of step n
     hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, w.st, (int64_t)n);
@@ -2113,6 +2484,10 @@ hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *con
         a.un[i] = (const T *)Un[i];
         a.out[i] = (T *)w.A[i];
     }
+    if (np > 0) {
+        hipLaunchKernelGGL(k_pre<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa);
+        launch_binning(c, np, w.qh, s);
+    }
     a.ra = (T)0.0;
     a.rb = (T)1.0;
     a.amp = w.st->amp[0];
@@ -2120,6 +2495,7 @@ hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *con
         hipLaunchKernelGGL((stage_kernel<T, 0, false, true>), dim3(nblk_all), dim3(STAGE_THREADS), 0, s, a);
     else
         hipLaunchKernelGGL((stage_kernel<T, 0, false, false>), dim3(nblk_all), dim3(STAGE_THREADS), 0, s, a);
+    stage_particles(0, w.A);
     for (int i = 0; i < 4; ++i) {
         a.in[i] = (const T *)w.A[i];
         a.out[i] = (T *)w.B[i];
@@ -2127,10 +2503,73 @@ hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *con
     a.ra = (T)0.75;
     a.rb = (T)0.25;
     a.amp = w.st->amp[1];
+    if (np > 0)
+        hipLaunchKernelGGL(k_omega<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa, (const T *)w.A[0]);
     if (full)
         hipLaunchKernelGGL((stage_kernel<T, 1, false, true>), dim3(nblk_all), dim3(STAGE_THREADS), 0, s, a);
     else
         hipLaunchKernelGGL((stage_kernel<T, 1, false, false>), dim3(nblk_all), dim3(STAGE_THREADS), 0, s, a);
+    stage_particles(1, w.B);
+
+    AdjPartArgs<T> pr{};
+    if (np > 0) {
+        // third stage into L1, its no-slip-corrected momentum into acc
+        for (int i = 0; i < 4; ++i) {
+            a.in[i] = (const T *)w.B[i];
+            a.out[i] = (T *)aw.L1[i];
+        }
+        a.ra = (T)(1.0 / 3.0);
+        a.rb = (T)(2.0 / 3.0);
+        a.amp = w.st->amp[2];
+        hipLaunchKernelGGL(k_omega<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa, (const T *)w.B[0]);
+        if (full)
+            hipLaunchKernelGGL((stage_kernel<T, 2, false, true>), dim3(nblk_all), dim3(STAGE_THREADS), 0, s, a);
+        else
+            hipLaunchKernelGGL((stage_kernel<T, 2, false, false>), dim3(nblk_all), dim3(STAGE_THREADS), 0, s, a);
+        stage_particles(2, aw.L1);
+        for (int i = 1; i < 4; ++i) {
+            const hipError_t e = hipMemcpyAsync(aw.acc[i], aw.L1[i], ncell * sizeof(T),
+                                                hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return e;
+        }
+        for (int i = 0; i < 4; ++i) pa.f[i] = (const T *)aw.L1[i];
+        hipLaunchKernelGGL(k_post<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa);
+        {
+            SparseArgs<T> sa = sparse_args<T>(c);
+            sa.val = w.du;
+            for (int i = 0; i < 3; ++i) sa.fields[i] = (T *)aw.acc[1 + i];
+            sa.drho = (const T *)aw.L1[0];
+            hipLaunchKernelGGL((k_sparse<T, SP_NOSLIP>), sgrid, dim3(SP_THREADS), 0, s, sa);
+        }
+        // substeps 7, 6, 5, 4 reversed
+        pr.G = Grid{p.nx, p.ny, p.nz, p.h, 1.0 / p.h, p.rho0};
+        pr.np = np;
+        pr.dt = p.dt;
+        pr.V = 8.0 * p.h * p.h * p.h;
+        pr.inv_h3 = 1.0 / (p.h * p.h * p.h);
+        pr.L[0] = p.nx * p.h;
+        pr.L[1] = p.ny * p.h;
+        pr.L[2] = p.nz * p.h;
+        for (int i = 0; i < 4; ++i) {
+            pr.Un[i] = (const T *)Un[i];
+            pr.U3[i] = (const T *)aw.L1[i];
+            pr.lam[i] = (T *)lam[i];
+        }
+        for (int i = 0; i < 3; ++i) pr.gnew[i] = (const T *)aw.acc[1 + i];
+        pr.q = aw.pq;
+        pr.u = pp->u;
+        pr.lq = pp->lq;
+        pr.lu = pp->lu;
+        pr.lF = pp->lF;
+        pr.me = w.me; pr.eps = w.eps; pr.ks = w.ks; pr.qeq = w.qeq; pr.qh = w.qh; pr.F = w.F;
+        pr.un = w.Vt; pr.du = w.du; pr.mf = w.mf;
+        pr.lqh = aw.plqh; pr.lFt = aw.plF; pr.lVt = aw.plVt; pr.lmf = aw.plmf;
+        pr.dme = aw.pdme; pr.deps = aw.pdeps; pr.dks = aw.pdks;
+        const dim3 pg(wave_blocks(np));
+        hipLaunchKernelGGL(k_adjp_final<T>, pg, dim3(256), 0, s, pr);
+        hipLaunchKernelGGL(k_adjp_noslip<T>, pg, dim3(256), 0, s, pr);
+        hipLaunchKernelGGL(k_adjp_velocity<T>, pg, dim3(256), 0, s, pr);
+    }
 
     // reverse the three stages: (stage input, adjoint in, adjoint out, cs, ds)
     const double tn = (double)n * p.dt;
@@ -2176,14 +2615,28 @@ hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *con
         x.gz = (p.nz + ADJ_TZ - 1) / ADJ_TZ;
         hipLaunchKernelGGL(k_adj_tile<T>, dim3(x.gx * x.gy * x.gz), dim3(ATHREADS), 0, s, x);
         hipLaunchKernelGGL(k_adj_rho<T>, dim3(nb), dim3(256), 0, s, x);
+        if (np > 0) {
+            pr.cs = cs[st];
+            pr.Us = (const T *)Uin[st][0];
+            for (int i = 0; i < 4; ++i) {
+                pr.lin[i] = (const T *)Lin[st][i];
+                pr.lam[i] = (T *)Lout[st][i];
+            }
+            hipLaunchKernelGGL(k_adjp_stage<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pr);
+        }
+    }
+    if (np > 0) {
+        for (int i = 0; i < 4; ++i) pr.lam[i] = (T *)lam[i];
+        hipLaunchKernelGGL(k_adjp_start<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pr);
     }
     hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, w.st, (int64_t)c->step);
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_step(ic_ctx *c, int64_t n, const void *const Un[4], void *const lam[4]) {
-    return c->p.prec == IC_FP64 ? adjoint_impl<double>(c, n, Un, lam)
-                                : adjoint_impl<float>(c, n, Un, lam);
+hipError_t launch_adjoint_step(ic_ctx *c, int64_t n, const void *const Un[4], void *const lam[4],
+                               const AdjParticles *pp) {
+    return c->p.prec == IC_FP64 ? adjoint_impl<double>(c, n, Un, lam, pp)
+                                : adjoint_impl<float>(c, n, Un, lam, pp);
 }
 
 hipError_t launch_step(ic_ctx *c, bool overlap, bool first, bool last) {

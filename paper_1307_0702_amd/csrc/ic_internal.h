@@ -78,6 +78,19 @@ struct Workspace {
 struct AdjWorkspace {
     void *L2[4], *L1[4], *acc[4], *murf[3], *mur;
     double *partial;   // [IC_MAX_MODES][adjoint_blocks]
+    // per particle, [N][3]: dL/dq^{n+1/2}, dL/dF^{n+1/2}, dL/dV~, dL/dm_f of
+    // the step being reversed; [N]: dL/dm_e, dL/deps_pf, dL/dk_s accumulated
+    // over reversed steps until read with reset
+    double *plqh, *plF, *plVt, *plmf, *pdme, *pdeps, *pdks;
+    double *pq;   // [N][3] the caller's q^n, wrapped into the box
+};
+// Particle arrays of one reversed step (device, [N][3]): the state q^n, u^n
+// before the step, the adjoints lq, lu (in: after the step, out: before) and
+// an optional seed dL/dF^{n+1/2}.
+struct AdjParticles {
+    const double *q, *u;
+    double *lq, *lu;
+    const double *lF;
 };
 // Partial-sum slots per mode: at least one per block of the momentum pass
 // (tiles of 32 x 8 columns and at least 16 planes) and never fewer than one
@@ -151,7 +164,9 @@ hipError_t launch_conserved(ic_ctx *c, double *host_out);
 hipError_t launch_set_step(ic_ctx *c);      // device step counter := c->step
 // Reverse of step n from the state U^n (device fields): lam (device, in:
 // dL/dU^{n+1}, out: dL/dU^n); drive gradient added to the adjoint partials.
-hipError_t launch_adjoint_step(ic_ctx *c, int64_t n, const void *const Un[4], void *const lam[4]);
+// pp: the particle arrays, or nullptr for a particle-free context.
+hipError_t launch_adjoint_step(ic_ctx *c, int64_t n, const void *const Un[4], void *const lam[4],
+                               const AdjParticles *pp);
 
 // Event pair around one stage launch when profiling (nullptr otherwise).
 hipEvent_t prof_event(ic_ctx *c);

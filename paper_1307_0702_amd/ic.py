@@ -29,6 +29,7 @@ EXPORTED = [
     "ic_eps_from_kappa_ratio", "ic_strerror", "ic_last_error", "ic_profile", "ic_profile_read",
     "ic_set_tile", "ic_get_tile", "ic_graph_create", "ic_graph_launch", "ic_graph_destroy",
     "ic_adjoint_workspace_size", "ic_bind_adjoint", "ic_adjoint_step", "ic_adjoint_drive",
+    "ic_adjoint_step_particles", "ic_adjoint_particle_grad", "ic_copy_particles", "ic_load_particles",
 ]
 
 
@@ -92,6 +93,11 @@ def load_library(path=LIB_PATH):
         "ic_bind_adjoint": ([P, P, ctypes.c_size_t], ctypes.c_int),
         "ic_adjoint_step": ([P, ctypes.c_int64, P, P, P, P, P, P, P, P], ctypes.c_int),
         "ic_adjoint_drive": ([P, dp, ctypes.c_int32], ctypes.c_int),
+        "ic_adjoint_step_particles": ([P, ctypes.c_int64, P, P, P, P, P, P, P, P, P, P, P, P, P],
+                                      ctypes.c_int),
+        "ic_adjoint_particle_grad": ([P, P, P, P, ctypes.c_int32], ctypes.c_int),
+        "ic_copy_particles": ([P, P, P], ctypes.c_int),
+        "ic_load_particles": ([P, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -224,6 +230,29 @@ def ic_adjoint_drive(ctx, nmodes, reset=False):
     out = (ctypes.c_double * IC_MAX_MODES)()
     _check(_lib.ic_adjoint_drive(ctx, out, int(bool(reset))), ctx)
     return np.array(list(out)[:int(nmodes)])
+
+
+def ic_adjoint_step_particles(ctx, n, U, q, u, lam, lq, lu, lF=None):
+    """U: the four state fields of step n; q, u: the particle state of step
+    n ([np][3] float64); lam, lq, lu: adjoints after the step in, before
+    the step out; lF: dL/dF^{n+1/2} or None.  All device tensors."""
+    _check(_lib.ic_adjoint_step_particles(ctx, int(n), *[_ptr(x) for x in U], _ptr(q), _ptr(u),
+                                          *[_ptr(x) for x in lam], _ptr(lq), _ptr(lu), _ptr(lF)), ctx)
+
+
+def ic_adjoint_particle_grad(ctx, n, reset=False):
+    """Accumulated (dL/dm_e, dL/deps_pf, dL/dk_s), host float64 [n] each."""
+    out = [np.zeros(n) for _ in range(3)]
+    _check(_lib.ic_adjoint_particle_grad(ctx, *[_ptr(x) for x in out], int(bool(reset))), ctx)
+    return tuple(out)
+
+
+def ic_copy_particles(ctx, q_dev, u_dev):
+    _check(_lib.ic_copy_particles(ctx, _ptr(q_dev), _ptr(u_dev)), ctx)
+
+
+def ic_load_particles(ctx, q_dev, u_dev):
+    _check(_lib.ic_load_particles(ctx, _ptr(q_dev), _ptr(u_dev)), ctx)
 
 
 def ic_interpolate(ctx, n, q_dev, kind, field_dev, out_dev):

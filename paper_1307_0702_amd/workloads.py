@@ -290,6 +290,26 @@ def gibbs_boltzmann_32(n_side=3, drho_amp=0.1, kT=1e-3, seed=5):
     return Workload("gibbs-boltzmann-32", fl, p, [mode], drho, g, nT)
 
 
+def adjoint_64(n=16, seed=5, amp=2.3e-4):
+    """64^3, kT = 0, the fluid at rest: n particles drawn as in
+    uniform_particles (masses and compressibilities on both sides of the
+    fluid's), tethered at their start positions; four cosine pressure drives
+    along x with m = 1..4 wavelengths in the box, each at its own discrete
+    resonance rounded to a whole-step period, pressure amplitude amp each.
+    period_steps is the period of the m = 1 drive."""
+    fl = Fluid(64, 64, 64, kT=0.0, seed=seed)
+    modes = []
+    for m in range(1, 5):
+        om = discrete_sound_frequency(fl, 0, m)
+        modes.append(Mode(axis=0, shape="cos", m=m, x0=0.0, amp=amp,
+                          omega=2.0 * math.pi / (period_steps(fl, om) * fl.dt)))
+    nT = period_steps(fl, modes[0].omega)
+    p = uniform_particles(fl, n, seed, ks=soft_tether(fl, modes[0].omega, 4.0))
+    drho = np.zeros(fl.shape)
+    g = np.zeros((3,) + fl.shape)
+    return Workload("adjoint-64", fl, p, modes, drho, g, nT)
+
+
 def ensemble(n=64, seed=4000, sizes=(32, 48, 64), max_particles=50, kT=1e-3):
     """n independent thermal replicas: grid edge drawn from `sizes`, 1 to
     max_particles free particles with m_p/(rho0 V) ~ U[0.5, 2] and

@@ -178,8 +178,8 @@ def test_adjoint_error_paths():
     assert e.value.code == ic.IC_E_ARG
     sim.set_particles(np.array([[3.0, 4.0, 5.0]]), np.array([0.0]), np.array([0.0]))
     with pytest.raises(ic.ICError) as e:
-        adj.step(0, U, lam)
-    assert e.value.code == ic.IC_E_STATE          # particles set
+        ic.ic_adjoint_step(sim.ctx, 0, list(U), list(lam))
+    assert e.value.code == ic.IC_E_STATE          # particles set: the particle entry point is needed
     hot = Simulation(W.Fluid(16, 16, 16, kT=1e-3, seed=3), prec="fp64")
     hadj = Adjoint(hot)
     with pytest.raises(ic.ICError) as e:

@@ -58,10 +58,16 @@ def test_thermal_workspace_holds_two_noise_sets():
 def test_adjoint_workspace_size():
     from paper_1307_0702_amd import ic
     n = 64
-    got = ic.ic_adjoint_workspace_size(_params(nx=n, ny=n, nz=n))
-    fields = 16 * n ** 3 * 8
-    partial = ic.IC_MAX_MODES * (n ** 3 // 256) * 8
-    assert got == fields + partial
+    def up(b):
+        return (b + 255) // 256 * 256
+
+    for npart in (4, 1000):
+        got = ic.ic_adjoint_workspace_size(_params(nx=n, ny=n, nz=n, max_particles=npart))
+        fields = 16 * n ** 3 * 8
+        partial = ic.IC_MAX_MODES * (n ** 3 // 256) * 8
+        # per particle: five [N][3] and three [N] doubles
+        particles = 5 * up(24 * npart) + 3 * up(8 * npart)
+        assert got == fields + partial + particles
 
 
 def test_bench_refuses_more_than_one_gpu():
