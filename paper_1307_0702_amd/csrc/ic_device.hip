@@ -1494,7 +1494,7 @@ __device__ __forceinline__ void cell_of(int j, int nx, int ny, int &x, int &y, i
 }
 
 // Momentum pass of the transposed stage increment: a tile of ATX x ATY
-// columns marches over tz = ADJ_TZ planes in z.  LDS holds three planes (k-1, k, k+1)
+// columns marches over tz planes in z (adjoint_tz).  LDS holds three planes (k-1, k, k+1)
 // of lambda_g, g and v = g / rho_face and three density planes (k, k+1, k+2)
 // over the tile plus a one-cell halo, so a cell's neighbour reads come from
 // LDS and each velocity is divided out once per point.  lambda_rho is read
@@ -1506,7 +1506,6 @@ __device__ __forceinline__ void cell_of(int j, int nx, int ny, int &x, int &y, i
 // is unrolled by three so every LDS slot is a compile-time constant.
 constexpr int ATX = 32, ATY = 8, ATHREADS = ATX * ATY;
 constexpr int APX = ATX + 2, APY = ATY + 2, APS = APX * APY;   // local x, y in [-1, AT]
-constexpr int ADJ_TZ = 32;
 constexpr int APTS = (APS + ATHREADS - 1) / ATHREADS;            // halo points per thread
 
 // Reciprocal for the adjoint's v = g / rho_face: the hardware estimate
@@ -2431,6 +2430,11 @@ hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *con
     const bool full = p.nx % TX == 0 && p.ny % TY == 0;
     const int np = pp ? c->np : 0;
     const dim3 sgrid(c->nblk[0], c->nblk[1], c->nblk[2]);
+    // every block of the momentum pass owns one partial-sum slot per mode
+    const int atz = adjoint_tz(p);
+    if ((long)((p.nx + ATX - 1) / ATX) * ((p.ny + ATY - 1) / ATY) * ((p.nz + atz - 1) / atz) >
+        adjoint_blocks(p))
+        return hipErrorInvalidValue;
     PartArgs<T> pa{};
     if (np > 0) {
         void *f[4] = {const_cast<void *>(Un[0]), const_cast<void *>(Un[1]),
@@ -2609,10 +2613,10 @@ hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *con
             x.dc.c[m] = cs[st] * sin(md.omega * ts[st] + md.phase);
         }
         x.nbp = adjoint_blocks(p);
-        x.tz = ADJ_TZ;
+        x.tz = atz;
         x.gx = (p.nx + ATX - 1) / ATX;
         x.gy = (p.ny + ATY - 1) / ATY;
-        x.gz = (p.nz + ADJ_TZ - 1) / ADJ_TZ;
+        x.gz = (p.nz + atz - 1) / atz;
         hipLaunchKernelGGL(k_adj_tile<T>, dim3(x.gx * x.gy * x.gz), dim3(ATHREADS), 0, s, x);
         hipLaunchKernelGGL(k_adj_rho<T>, dim3(nb), dim3(256), 0, s, x);
         if (np > 0) {

@@ -92,12 +92,32 @@ struct AdjParticles {
     double *lq, *lu;
     const double *lF;
 };
-// Partial-sum slots per mode: at least one per block of the momentum pass
-// (tiles of 32 x 8 columns and at least 16 planes) and never fewer than one
-// per 256 cells.
+// z extent of a block of the adjoint's momentum pass (tiles of 32 x 8
+// columns): minimises rounds of resident blocks (4 per CU in FP32, 2 in
+// FP64, 256 CUs) times planes marched (the extent plus the two planes of the
+// prologue); ties go to the larger extent.
+constexpr int ADJ_TZ_MIN = 2;
+inline int adjoint_tz(const ic_params &p) {
+    const long cols = (long)((p.nx + 31) / 32) * ((p.ny + 7) / 8);
+    const long cap = 256L * (p.prec == IC_FP64 ? 2 : 4);
+    int best = 32;
+    long best_cost = -1;
+    for (int tz = 32; tz >= ADJ_TZ_MIN; tz /= 2) {
+        const long blocks = cols * ((p.nz + tz - 1) / tz);
+        const long cost = ((blocks + cap - 1) / cap) * ((tz < p.nz ? tz : p.nz) + 2);
+        if (best_cost < 0 || cost < best_cost) {
+            best = tz;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+// Partial-sum slots per mode: at least one per block of the momentum pass at
+// the smallest z extent, and never fewer than one per 256 cells.
 inline int adjoint_blocks(const ic_params &p) {
     const long cells = ((long)p.nx * p.ny * p.nz + 255) / 256;
-    const long tiles = (long)((p.nx + 31) / 32) * ((p.ny + 7) / 8) * ((p.nz + 15) / 16);
+    const long tiles = (long)((p.nx + 31) / 32) * ((p.ny + 7) / 8) *
+                       ((p.nz + ADJ_TZ_MIN - 1) / ADJ_TZ_MIN);
     return (int)(cells > tiles ? cells : tiles);
 }
 size_t adjoint_workspace_bytes(const ic_params &p);
