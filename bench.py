@@ -294,8 +294,8 @@ def run_adjoint_particles(prec, periods, fd_check):
     epst = torch.tensor(eps, dtype=torch.float64)
     fixed = dict(ks=p.ks, qeq=p.qeq, fext=p.fext)
 
-    def loss(amps_, me_, eps_):
-        _, _, _, F = rollout_particles(adj, U0, q0, u0, amps_, me_, eps_, md, 0, nsteps, 64, **fixed)
+    def loss(amps_, me_, eps_, every=64):
+        _, _, _, F = rollout_particles(adj, U0, q0, u0, amps_, me_, eps_, md, 0, nsteps, every, **fixed)
         return -F[:, 0].mean()     # mean x-component of -F_tether (f_ext = 0)
 
     torch.cuda.synchronize()
@@ -313,6 +313,15 @@ def run_adjoint_particles(prec, periods, fd_check):
     t_grad = time.perf_counter() - t0
     dA, dme, deps = (x.grad.numpy() for x in xs)
     dkr = -fl.cf ** 2 / kr ** 2 * deps          # eps = cf^2 (1/r - 1)
+    # the same gradient with the whole trajectory kept in device memory
+    every_all = adj.auto_every(nsteps)
+    ys = [x.detach().clone().requires_grad_(True) for x in xs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss(*ys, every="auto").backward()
+    torch.cuda.synchronize()
+    t_grad_all = time.perf_counter() - t0
+    same = max(float((y.grad - x.grad).abs().max() / x.grad.abs().max()) for x, y in zip(xs, ys))
     out = dict(metric="adjoint particle-steps/s", value=p.n * nsteps / t_grad, unit="particle-steps/s",
                n_gpus=1, steps=nsteps, warmup=0, ms_per_step=t_grad * 1e3 / nsteps,
                higher_is_better=True, scaling="weak", vs_baseline=None,
@@ -321,6 +330,10 @@ def run_adjoint_particles(prec, periods, fd_check):
                            drives=4, periods=periods, checkpoint_every=64),
                forward_step_ms=fwd, adjoint_step_ms=rev, adjoint_step_over_forward_step=rev / fwd,
                forward_run_s=t_fwd, gradient_run_s=t_grad, gradient_over_forward_run=t_grad / t_fwd,
+               trajectory_in_memory=dict(every=every_all, state_bytes=adj.state_bytes(),
+                                         gradient_run_s=t_grad_all,
+                                         gradient_over_forward_run=t_grad_all / t_fwd,
+                                         max_rel_diff_to_every_64=same),
                loss=L0, dL_damp=dA.tolist(), dL_dmp=dme.tolist(), dL_dkappa_ratio=dkr.tolist())
     if fd_check:
         rng = np.random.default_rng(7)

@@ -72,10 +72,26 @@ class Adjoint:
             ic.ic_load_particles(self.sim.ctx, q, u)
         self.sim.set_step(n)
 
+    def state_bytes(self):
+        """Device bytes of one checkpoint (fields, positions, velocities)."""
+        sim = self.sim
+        return sim.U.numel() * sim.U.element_size() + 2 * 3 * 8 * sim.np
+
+    def auto_every(self, nsteps, fraction=0.5):
+        """Checkpoint spacing for nsteps steps: 1 (every state kept, no
+        re-stepping in the reversal) when the whole trajectory fits in
+        `fraction` of the free device memory, else 64."""
+        free, _ = self.sim.torch.cuda.mem_get_info(self.sim.device)
+        return 1 if nsteps * self.state_bytes() <= fraction * free else 64
+
     def forward(self, U0, n0, nsteps, every=64, q0=None, u0=None):
         """Steps the simulation from U0 (and, with particles, q0, u0) at step
         n0; returns the final fields and the checkpoints {step: (U, q, u)}.
-        The final particle state is in self.final."""
+        every="auto" picks the spacing with auto_every.  The final particle
+        state is in self.final."""
+        if every == "auto":
+            every = self.auto_every(nsteps)
+        self.every = every
         self.restore((U0, q0, u0), n0)
         ckpt = {}
         for s in range(nsteps):
@@ -93,14 +109,17 @@ class Adjoint:
         particle_grad).  Re-stepping overwrites the bound state and the step
         counter."""
         sim = self.sim
+        if every == "auto":
+            every = self.every
         starts = sorted(ckpt)
         for c0 in reversed(starts):
             seg = min(every, n0 + nsteps - c0)
             states = [ckpt[c0]]
-            self.restore(ckpt[c0], c0)
-            for _ in range(seg - 1):
-                sim.step(1)
-                states.append(self.snapshot())
+            if seg > 1:
+                self.restore(ckpt[c0], c0)
+                for _ in range(seg - 1):
+                    sim.step(1)
+                    states.append(self.snapshot())
             for k in reversed(range(seg)):
                 U, q, u = states[k]
                 self.step(c0 + k, U, lam, q, u, lq, lu, lF)
@@ -126,7 +145,7 @@ def rollout(adj, U0, amps, modes, n0, nsteps, every=64):
                     m["amp"] = a
                 adj_.sim.set_forcing(md)
                 UN, ck = adj_.forward(U0_.detach(), n0_, nsteps_, every_)
-                ctx.adj, ctx.ck, ctx.n0, ctx.ns, ctx.every = adj_, ck, n0_, nsteps_, every_
+                ctx.adj, ctx.ck, ctx.n0, ctx.ns, ctx.every = adj_, ck, n0_, nsteps_, adj_.every
                 ctx.nmodes = len(md)
                 ctx.md = md
                 return UN
@@ -175,7 +194,7 @@ def rollout_particles(adj, U0, q0, u0, amps, me, eps, modes, n0, nsteps, every=6
                 tether, _, _ = sim.avg_force(reset=True)   # mean of k_s minimg(q^{n+1/2} - q_eq)
                 f0 = np.zeros((sim.np, 3)) if fext_ is None else np.asarray(fext_, dtype=np.float64)
                 Fmean = torch.as_tensor(f0 - tether, dtype=torch.float64, device=U0_.device)
-                ctx.adj, ctx.ck, ctx.n0, ctx.ns, ctx.every = adj_, ck, n0_, nsteps_, every_
+                ctx.adj, ctx.ck, ctx.n0, ctx.ns, ctx.every = adj_, ck, n0_, nsteps_, adj_.every
                 ctx.md = md
                 _, qN, uN = adj_.final
                 return UN, qN, uN, Fmean

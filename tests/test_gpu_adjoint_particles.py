@@ -131,9 +131,10 @@ def test_one_reversed_step_with_particles_matches_oracle(prec, shape, tol):
     assert np.array_equal(q_after, P["q"])
 
 
-def test_checkpointed_reversal_with_particles_matches_oracle_run_grad():
+@pytest.mark.parametrize("every", [3, "auto"])
+def test_checkpointed_reversal_with_particles_matches_oracle_run_grad(every):
     shape = (30, 20, 16)
-    print(f"particle adjoint, 7 steps checkpointed every 3, {shape}", flush=True)
+    print(f"particle adjoint, 7 steps checkpointed every {every}, {shape}", flush=True)
     fl, sim, adj, drho, g, lr, lg, P, sd = _setup(shape, "fp64", 520, npart=5)
     n0, nsteps = 2, 7
     qd, ud = _d64(sim, P["q"]), _d64(sim, P["u"])
@@ -141,13 +142,14 @@ def test_checkpointed_reversal_with_particles_matches_oracle_run_grad():
     ic.ic_copy_particles(sim.ctx, qd, ud)
     P = dict(P, q=qd.cpu().numpy(), u=ud.cpu().numpy())
     U0 = _dev(sim, drho, g)
-    UN, ck = adj.forward(U0, n0, nsteps, every=3, q0=qd, u0=ud)
-    assert sorted(ck) == [2, 5, 8]
+    UN, ck = adj.forward(U0, n0, nsteps, every=every, q0=qd, u0=ud)
+    # "auto" keeps the whole (small) trajectory: no re-stepping
+    assert sorted(ck) == ([2, 5, 8] if every == 3 else list(range(2, 9)))
     lam = _dev(sim, lr, lg)
     lq, lu, lF = _d64(sim, sd["lq"]), _d64(sim, sd["lu"]), _d64(sim, sd["lF"])
     adj.drive_grad(len(MODES), reset=True)
     adj.particle_grad(reset=True)
-    adj.backward(lam, n0, nsteps, ck, every=3, lq=lq, lu=lu, lF=lF)
+    adj.backward(lam, n0, nsteps, ck, every=every, lq=lq, lu=lu, lF=lF)
     sim.synchronize()
     want, final = OA.run_grad_particles(_state(drho, g, P, n0), fl.as_dict(), MODES, nsteps,
                                         cr=lr, cg=list(lg), cq=sd["lq"], cu=sd["lu"], cF=sd["lF"])

@@ -110,6 +110,14 @@ def test_fp64_plane_drive_nonoverlapping_particles_10_steps():
     _run_both(w, 10, check_every=5)
 
 
+def test_fp64_thermal_particles_500_steps():
+    # the long horizon of the parity bar: thermal noise, six particles (some
+    # kernels overlapping), a cosine and a plane drive; checked at 100 and 500
+    w = W.small_random(nx=22, ny=18, nz=14, npart=6, seed=55, kT=1e-3)
+    w.modes.append(W.Mode(axis=1, shape="plane", m=1, x0=5.0, amp=2e-3, omega=0.45, phase=0.2))
+    _run_both(w, 500, check_every=100)
+
+
 def test_fp64_grid_smaller_than_tile():
     w = W.small_random(nx=6, ny=5, nz=4, npart=2, seed=9, kT=1e-3)
     _run_both(w, 3)
