@@ -85,7 +85,7 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_gpu(w, prec, steps, warmup):
+def run_gpu(w, prec, steps, warmup, graph=True):
     import torch
 
     from paper_1307_0702_amd import ic
@@ -135,14 +135,16 @@ def run_gpu(w, prec, steps, warmup):
         finite=finite,
     )
     # the same steps replayed from one HIP graph (single-stream steps)
-    g = ic.ic_graph_create([sim.ctx], 50)
-    ic.ic_graph_launch(g, stream.cuda_stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ic.ic_graph_launch(g, stream.cuda_stream)
-    torch.cuda.synchronize()
-    res["graph_ms_per_step"] = (time.perf_counter() - t0) * 1e3 / 50
-    ic.ic_graph_destroy(g)
+    res["graph_ms_per_step"] = None
+    if graph:
+        g = ic.ic_graph_create([sim.ctx], 50)
+        ic.ic_graph_launch(g, stream.cuda_stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ic.ic_graph_launch(g, stream.cuda_stream)
+        torch.cuda.synchronize()
+        res["graph_ms_per_step"] = (time.perf_counter() - t0) * 1e3 / 50
+        ic.ic_graph_destroy(g)
     log(f"[bench] {prec}: {res['ms_per_step']:.3f} ms/step, stage kernel "
         f"{res['stage_ms_per_launch']:.3f} ms/launch, {res['stage_achieved_gbs']:.0f} GB/s")
     del sim
@@ -638,6 +640,8 @@ def main():
     ap.add_argument("--periods", type=int, default=20,
                     help="adjoint-64: drive periods the loss averages over")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the graph-replayed step (a kernel trace then holds only the timed launches)")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--stats-summary", metavar="CSV")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"))
@@ -684,7 +688,7 @@ def main():
     res = {}
     precs = ["fp32", "fp64"] if args.prec == "both" else [args.prec]
     for prec in precs:
-        res[prec] = run_gpu(w, prec, args.steps, args.warmup)
+        res[prec] = run_gpu(w, prec, args.steps, args.warmup, graph=not args.no_graph)
     main_prec = precs[0]
     r = res[main_prec]
     out = dict(

@@ -241,6 +241,22 @@ def test_particle_adjoint_error_paths():
     with pytest.raises(ic.ICError) as e:
         ic.ic_adjoint_step_particles(sim.ctx, -1, list(U), z, z, list(lam), z, z)
     assert e.value.code == ic.IC_E_ARG
+    # positions are checked before they index the grid: on the host when
+    # loaded, on the device (replaced by 0, reported by the next
+    # synchronising call) when handed to a reversed step
+    bad = z.clone()
+    bad[0, 1] = float("nan")
+    with pytest.raises(ic.ICError) as e:
+        ic.ic_load_particles(sim.ctx, bad, z)
+    assert e.value.code == ic.IC_E_ARG
+    ic.ic_load_particles(sim.ctx, z + 20.5, z)                   # wrapped into the box
+    q_in, _ = sim.get_particles()
+    assert np.allclose(q_in, 4.5)
+    ic.ic_adjoint_step_particles(sim.ctx, 0, list(U), bad, z, list(lam), z.clone(), z.clone())
+    with pytest.raises(ic.ICError) as e:
+        ic.ic_adjoint_particle_grad(sim.ctx, 1)
+    assert e.value.code == ic.IC_E_ARG
+    ic.ic_adjoint_particle_grad(sim.ctx, 1)                      # the flag was cleared
     hot = Simulation(W.Fluid(16, 16, 16, kT=1e-3, seed=3), prec="fp64", max_particles=1)
     Adjoint(hot)
     with pytest.raises(ic.ICError) as e:
