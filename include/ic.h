@@ -47,7 +47,7 @@ enum {
 enum { IC_FP32 = 1, IC_FP64 = 2 };
 
 /* Grid location of a field for ic_interpolate / ic_spread. */
-enum { IC_CELL = 0, IC_FACE_X = 1, IC_FACE_Y = 2, IC_FACE_Z = 3 };
+enum { IC_CELL = 0, IC_FACE_X = 1, IC_FACE_Y = 2, IC_FACE_Z = 3, IC_FACES = 4 };
 
 /* Shape of an imposed pressure drive. */
 enum { IC_MODE_COS = 0, IC_MODE_PLANE = 1 };
@@ -157,7 +157,10 @@ int ic_step(ic_ctx *ctx, int64_t nsteps);
 /* Averaging operator J (Sec. II, Eq. Jdis; staggered positions of App. A):
  * out[p] = sum_i h^3 theta_h(q_p - r_i) field[i] for n positions q ([n][3],
  * device) and a field of the given location kind (device, context
- * precision, nx*ny*nz).  out is device, double[n].  Asynchronous. */
+ * precision, nx*ny*nz).  out is device, double[n].  With kind IC_FACES,
+ * field holds the x, y and z face components one after another (3 nx*ny*nz,
+ * e.g. the momentum of a state) and out is double[n][3], the averaged
+ * vector J_alpha f^alpha.  Asynchronous. */
 int ic_interpolate(ic_ctx *ctx, int32_t n, const double *q, int32_t kind,
                    const void *field, double *out);
 
@@ -168,6 +171,18 @@ int ic_interpolate(ic_ctx *ctx, int32_t n, const double *q, int32_t kind,
  * context workspace, so it must not overlap an ic_step of the context. */
 int ic_spread(ic_ctx *ctx, int32_t n, const double *q, const double *f, int32_t kind,
               void *field);
+
+/* Snapshot and restore of the bound state (checkpoints, fault injection):
+ * ic_get_state copies the four fields (nx*ny*nz each, context precision)
+ * and the particle positions and velocities ([n][3] doubles) into caller
+ * device buffers; any pointer may be NULL.  Asynchronous.  ic_set_state
+ * copies them back in from caller device buffers (NULL: keep); positions are
+ * checked on the host and wrapped into the box (IC_E_ARG if one is not
+ * finite).  Synchronising.  Neither touches the step counter (ic_set_step),
+ * the particle parameters or the force averages. */
+int ic_get_state(ic_ctx *ctx, void *drho, void *gx, void *gy, void *gz, double *q, double *u);
+int ic_set_state(ic_ctx *ctx, const void *drho, const void *gx, const void *gy, const void *gz,
+                 const double *q, const double *u);
 
 /* Window averages since the last reset, per particle ([n][3], host, either
  * may be NULL): the mean of -F_tether = k_s minimg(q^{n+1/2} - q_eq), the

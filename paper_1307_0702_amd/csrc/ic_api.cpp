@@ -505,7 +505,7 @@ int ic_interpolate(ic_ctx *c, int32_t n, const double *q, int32_t kind, const vo
                    double *out) {
     if (!c) return IC_E_ARG;
     if (n < 0) return fail(c, IC_E_ARG, "n < 0");
-    if (kind < IC_CELL || kind > IC_FACE_Z) return fail(c, IC_E_ARG, "bad kind");
+    if (kind < IC_CELL || kind > IC_FACES) return fail(c, IC_E_ARG, "bad kind");
     if (n == 0) return IC_OK;
     if (!q || !field || !out) return fail(c, IC_E_ARG, "NULL pointer");
     hipError_t e = launch_interpolate(c, n, q, kind, field, out);
@@ -681,6 +681,35 @@ int ic_adjoint_particle_grad(ic_ctx *c, double *dme, double *deps, double *dks, 
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint particle gradients");
     return take_flag(c);
+}
+
+int ic_get_state(ic_ctx *c, void *drho, void *gx, void *gy, void *gz, double *q, double *u) {
+    int rc = check_bound(c);
+    if (rc != IC_OK) return rc;
+    const size_t fb = (size_t)c->p.nx * c->p.ny * c->p.nz * (c->p.prec == IC_FP64 ? 8 : 4);
+    void *dst[4] = {drho, gx, gy, gz};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 4 && e == hipSuccess; ++i)
+        if (dst[i]) e = hipMemcpyAsync(dst[i], c->f[i], fb, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "get_state");
+    return ic_copy_particles(c, q, u);
+}
+
+int ic_set_state(ic_ctx *c, const void *drho, const void *gx, const void *gy, const void *gz,
+                 const double *q, const double *u) {
+    int rc = check_bound(c);
+    if (rc != IC_OK) return rc;
+    const size_t fb = (size_t)c->p.nx * c->p.ny * c->p.nz * (c->p.prec == IC_FP64 ? 8 : 4);
+    const void *src[4] = {drho, gx, gy, gz};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 4 && e == hipSuccess; ++i)
+        if (src[i]) e = hipMemcpyAsync(c->f[i], src[i], fb, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "set_state");
+    rc = ic_load_particles(c, q, u);
+    if (rc != IC_OK) return rc;
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "set_state");
+    return IC_OK;
 }
 
 int ic_copy_particles(ic_ctx *c, double *q, double *u) {

@@ -1076,12 +1076,26 @@ __global__ __launch_bounds__(256) void k_interp(const Grid G, int np, const doub
     const double qq[3] = {wrap_pos(q[3 * p], L[0]), wrap_pos(q[3 * p + 1], L[1]),
                           wrap_pos(q[3 * p + 2], L[2])};
     const WaveKernel k = wave_kernel(G, qq);
-    size_t i;
-    double w;
-    wave_point(G, k, kind, lane < 27 ? lane : 0, &i, &w);
-    double s = lane < 27 ? w * (double)field[i] : 0.0;
-    s = wave_sum(s);
-    if (lane == 0) out[p] = s;
+    if (kind != IC_FACES) {
+        size_t i;
+        double w;
+        wave_point(G, k, kind, lane < 27 ? lane : 0, &i, &w);
+        double s = lane < 27 ? w * (double)field[i] : 0.0;
+        s = wave_sum(s);
+        if (lane == 0) out[p] = s;
+        return;
+    }
+    // three consecutive face fields (x, y, z components), out [n][3]
+    const size_t ncell = (size_t)G.nx * G.ny * G.nz;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        size_t i;
+        double w;
+        wave_point(G, k, 1 + ax, lane < 27 ? lane : 0, &i, &w);
+        double s = lane < 27 ? w * (double)field[ax * ncell + i] : 0.0;
+        s = wave_sum(s);
+        if (lane == 0) out[3 * p + ax] = s;
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libic.so")
 
 IC_OK, IC_E_ARG, IC_E_UNSTABLE, IC_E_MASS, IC_E_STATE, IC_E_HIP, IC_E_CAPACITY = 0, -1, -2, -3, -4, -5, -6
 IC_FP32, IC_FP64 = 1, 2
-IC_CELL, IC_FACE_X, IC_FACE_Y, IC_FACE_Z = 0, 1, 2, 3
+IC_CELL, IC_FACE_X, IC_FACE_Y, IC_FACE_Z, IC_FACES = 0, 1, 2, 3, 4
 IC_MODE_COS, IC_MODE_PLANE = 0, 1
 IC_MAX_MODES = 8
 
@@ -30,6 +30,7 @@ EXPORTED = [
     "ic_set_tile", "ic_get_tile", "ic_graph_create", "ic_graph_launch", "ic_graph_destroy",
     "ic_adjoint_workspace_size", "ic_bind_adjoint", "ic_adjoint_step", "ic_adjoint_drive",
     "ic_adjoint_step_particles", "ic_adjoint_particle_grad", "ic_copy_particles", "ic_load_particles",
+    "ic_get_state", "ic_set_state",
 ]
 
 
@@ -97,6 +98,8 @@ def load_library(path=LIB_PATH):
                                       ctypes.c_int),
         "ic_adjoint_particle_grad": ([P, P, P, P, ctypes.c_int32], ctypes.c_int),
         "ic_copy_particles": ([P, P, P], ctypes.c_int),
+        "ic_get_state": ([P, P, P, P, P, P, P], ctypes.c_int),
+        "ic_set_state": ([P, P, P, P, P, P, P], ctypes.c_int),
         "ic_load_particles": ([P, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -247,6 +250,17 @@ def ic_adjoint_particle_grad(ctx, n, reset=False):
     return tuple(out)
 
 
+def ic_get_state(ctx, fields, q_dev=None, u_dev=None):
+    """fields: four device tensors (or None) receiving (drho, gx, gy, gz)."""
+    f = list(fields) if fields is not None else [None] * 4
+    _check(_lib.ic_get_state(ctx, *[_ptr(x) for x in f], _ptr(q_dev), _ptr(u_dev)), ctx)
+
+
+def ic_set_state(ctx, fields, q_dev=None, u_dev=None):
+    f = list(fields) if fields is not None else [None] * 4
+    _check(_lib.ic_set_state(ctx, *[_ptr(x) for x in f], _ptr(q_dev), _ptr(u_dev)), ctx)
+
+
 def ic_copy_particles(ctx, q_dev, u_dev):
     _check(_lib.ic_copy_particles(ctx, _ptr(q_dev), _ptr(u_dev)), ctx)
 
@@ -381,7 +395,7 @@ class Simulation:
     def interpolate(self, q, kind, field):
         t = self.torch
         qd = t.as_tensor(np.ascontiguousarray(q, dtype=np.float64)).to(self.device)
-        out = t.zeros(len(q), dtype=t.float64, device=self.device)
+        out = t.zeros((len(q), 3) if kind == IC_FACES else len(q), dtype=t.float64, device=self.device)
         fd = field if isinstance(field, t.Tensor) else t.as_tensor(np.asarray(field)).to(self.dtype).to(self.device)
         fd = fd.contiguous()
         ic_interpolate(self.ctx, len(q), qd, kind, fd, out)

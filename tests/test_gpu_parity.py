@@ -199,6 +199,55 @@ def test_interpolate_and_spread_match_oracle(kind):
     assert _rel(out.cpu().numpy(), want_s) < 1e-13
 
 
+def test_interpolate_faces_is_the_three_face_kernels():
+    from paper_1307_0702_amd import ic
+    from paper_1307_0702_amd.ic import Simulation
+    fl = W.Fluid(29, 21, 18, h=1.0)
+    rng = np.random.default_rng(44)
+    sim = Simulation(fl, prec="fp32", max_particles=8)
+    L = np.array([fl.nx, fl.ny, fl.nz]) * fl.h
+    q = rng.random((40, 3)) * L
+    g = rng.standard_normal((3,) + fl.shape).astype(np.float32)
+    got = sim.interpolate(q, ic.IC_FACES, g)
+    assert got.shape == (40, 3)
+    for a in range(3):
+        one = sim.interpolate(q, ic.IC_FACE_X + a, g[a])
+        assert np.array_equal(got[:, a], one)
+        want = O.interpolate(g[a].astype(np.float64), q, fl.h, a)
+        assert _rel(got[:, a], want) < 1e-13
+
+
+def test_get_and_set_state_resume_bit_for_bit():
+    # a snapshot taken after 3 steps and restored later (with the step
+    # counter) reproduces the continued trajectory exactly
+    import torch
+    from paper_1307_0702_amd import ic
+    w = W.small_random(nx=30, ny=18, nz=20, npart=5, seed=61, kT=1e-3)
+    sim = _sim(w)
+    sim.step(3)
+    snap = [torch.empty_like(sim.U[i]) for i in range(4)]
+    q = torch.empty((w.particles.n, 3), dtype=torch.float64, device=sim.device)
+    u = torch.empty_like(q)
+    ic.ic_get_state(sim.ctx, snap, q, u)
+    sim.step(4)
+    r1, g1 = sim.get_state()
+    q1, u1 = sim.get_particles()
+    sim.U.zero_()
+    ic.ic_set_state(sim.ctx, snap, q, u)
+    sim.set_step(3)
+    sim.step(4)
+    r2, g2 = sim.get_state()
+    q2, u2 = sim.get_particles()
+    assert np.array_equal(r1, r2) and np.array_equal(q1, q2) and np.array_equal(u1, u2)
+    for c in range(3):
+        assert np.array_equal(g1[c], g2[c])
+    bad = q.clone()
+    bad[2, 0] = float("inf")
+    with pytest.raises(ic.ICError) as e:
+        ic.ic_set_state(sim.ctx, None, bad, None)
+    assert e.value.code == ic.IC_E_ARG
+
+
 def test_bitwise_repeatable():
     w = W.small_random(nx=40, ny=16, nz=36, npart=10, seed=23, kT=1e-3)
     a = _sim(w)
