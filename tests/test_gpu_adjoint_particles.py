@@ -309,3 +309,55 @@ def test_force_loss_gradient_on_the_64cube_workload():
         an = float((xs[i].grad * d).sum())
         print(f"  {name}: fd {fd:.10e} adjoint {an:.10e}", flush=True)
         assert abs(fd - an) <= 1e-4 * abs(fd), (name, fd, an)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 1.2e-4)])
+def test_force_loss_gradient_on_the_64cube_workload_matches_oracle(prec, tol):
+    # The reverse-mode benchmark's configuration from a developed state (one
+    # drive period stepped on the GPU): the gradient of the mean x-force over
+    # 12 steps in the drive amplitudes, m_e, eps, the initial positions and
+    # the initial fields, against the FP64 oracle's run_grad_particles from
+    # the same state.  FP32 bar: the per-step bar 1e-5 over 12 steps.
+    import torch
+    from paper_1307_0702_amd import ic
+    from paper_1307_0702_amd.adjoint import Adjoint, rollout_particles
+    from paper_1307_0702_amd.ic import Simulation
+    w = W.adjoint_64()
+    fl, p = w.fluid, w.particles
+    md = [m.as_dict() for m in w.modes]
+    eps = np.array([ic.ic_eps_from_kappa_ratio(fl.cf, r) for r in p.kappa_ratio])
+    sim = Simulation(fl, prec=prec, max_particles=p.n)
+    sim.set_particles(p.q, p.me, eps, ks=p.ks, qeq=p.qeq, fext=p.fext)
+    sim.set_forcing(md)
+    n0, nsteps = w.period_steps, 12
+    print(f"64^3 workload {prec}: {n0} steps to a developed state", flush=True)
+    sim.step(n0)
+    U0 = sim.U.clone()
+    q0 = torch.empty((p.n, 3), dtype=torch.float64, device=sim.device)
+    u0 = torch.empty_like(q0)
+    ic.ic_get_state(sim.ctx, None, q0, u0)
+    adj = Adjoint(sim)
+    base = [torch.tensor([m["amp"] for m in md], dtype=torch.float64),
+            torch.tensor(p.me, dtype=torch.float64), torch.tensor(eps, dtype=torch.float64)]
+    xs = [U0.clone().requires_grad_(True), q0.clone().requires_grad_(True)] + \
+         [b.clone().requires_grad_(True) for b in base]
+    _, _, _, F = rollout_particles(adj, xs[0], xs[1], u0, xs[2], xs[3], xs[4], md, n0, nsteps, 4,
+                                   ks=p.ks, qeq=p.qeq, fext=p.fext)
+    (-F[:, 0].mean()).backward()
+    U = U0.double().cpu().numpy()
+    st = dict(drho=U[0], g=[U[1], U[2], U[3]], n=n0, q=q0.cpu().numpy(), u=u0.cpu().numpy(),
+              me=np.asarray(p.me, float), eps=eps, ks=np.asarray(p.ks, float),
+              qeq=np.asarray(p.qeq, float), fext=np.asarray(p.fext, float))
+    cF = np.zeros((p.n, 3))
+    cF[:, 0] = -1.0 / (p.n * nsteps)
+    print("  oracle gradient", flush=True)
+    want, _ = OA.run_grad_particles(st, fl.as_dict(), md, nsteps, cF=cF)
+    got_U = xs[0].grad.double().cpu().numpy()
+    errs = {"A": _rel(xs[2].grad.numpy(), want["dA"]), "me": _rel(xs[3].grad.numpy(), want["dme"]),
+            "eps": _rel(xs[4].grad.numpy(), want["deps"]), "q0": _rel(xs[1].grad.cpu().numpy(), want["lq"]),
+            "drho0": _rel(got_U[0], want["lr"])}
+    for a in range(3):
+        errs["g%d" % a] = _rel(got_U[1 + a], want["lg"][a])
+    print("  ", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= tol, (k, v)
