@@ -69,3 +69,40 @@ def test_eps_from_kappa_ratio():
     assert ic.ic_eps_from_kappa_ratio(1.0, 0.5) == pytest.approx(1.0)
     assert ic.ic_eps_from_kappa_ratio(4.0, 0.25) == pytest.approx(48.0)
     assert ic._lib.ic_strerror(-3).decode().startswith("non-positive mass")
+
+
+def test_unbound_and_null_contexts_are_refused_before_device_work():
+    # every entry point that needs bound buffers refuses an unbound context
+    # with IC_E_STATE, and a NULL context with IC_E_ARG, without touching
+    # the device
+    from paper_1307_0702_amd import ic
+    L = ic._lib
+    ctx = ic.ic_create(_params(), 0)
+    null = ctypes.c_void_p()
+    buf = (ctypes.c_double * 12)()
+    i64 = ctypes.c_int64()
+    calls = {
+        "ic_step": lambda c: L.ic_step(c, 1),
+        "ic_set_particles": lambda c: L.ic_set_particles(c, 1, buf, None, buf, buf, None, None, None),
+        "ic_get_particles": lambda c: L.ic_get_particles(c, buf, buf),
+        "ic_get_state": lambda c: L.ic_get_state(c, None, None, None, None, buf, buf),
+        "ic_set_state": lambda c: L.ic_set_state(c, None, None, None, None, buf, buf),
+        "ic_copy_particles": lambda c: L.ic_copy_particles(c, buf, buf),
+        "ic_load_particles": lambda c: L.ic_load_particles(c, buf, buf),
+        "ic_adjoint_step": lambda c: L.ic_adjoint_step(c, 0, buf, buf, buf, buf, buf, buf, buf, buf),
+        "ic_adjoint_step_particles": lambda c: L.ic_adjoint_step_particles(
+            c, 0, buf, buf, buf, buf, buf, buf, buf, buf, buf, buf, buf, buf, None),
+        "ic_spread": lambda c: L.ic_spread(c, 1, buf, buf, 0, buf),
+        "ic_avg_force": lambda c: L.ic_avg_force(c, buf, buf, ctypes.byref(i64), 0),
+    }
+    for name, call in calls.items():
+        assert call(ctx) == ic.IC_E_STATE, name
+        assert call(null) == ic.IC_E_ARG, name
+    # the adjoint accumulators need a bound adjoint workspace
+    assert L.ic_adjoint_particle_grad(ctx, buf, buf, buf, 0) == ic.IC_E_STATE
+    assert L.ic_adjoint_drive(ctx, buf, 0) == ic.IC_E_STATE
+    assert L.ic_adjoint_particle_grad(null, buf, buf, buf, 0) == ic.IC_E_ARG
+    # bad interpolation kinds are refused before any launch
+    assert L.ic_interpolate(ctx, 1, buf, 5, buf, buf) == ic.IC_E_ARG
+    assert L.ic_interpolate(ctx, 1, buf, -1, buf, buf) == ic.IC_E_ARG
+    ic.ic_destroy(ctx)
