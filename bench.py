@@ -43,6 +43,7 @@ import argparse
 import csv
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -360,6 +361,67 @@ def run_adjoint_particles(prec, periods, fd_check):
     return out
 
 
+def run_force_sweeps(nwarm=40000, nper=8):
+    """The force figures of Sec. VI as one ensemble (FP64, kT = 0): every
+    configuration of workloads.force_sweeps_32 (26 symmetric pairs on 32^3
+    boxes) advances in the same HIP-graph launches.  After nwarm steps the
+    mean tether force is taken over nper drive periods, and each box's wave
+    amplitude from 3 samples a third of a period apart (the mean of a^2 over
+    them is exact for a sinusoid).  Gor'kov: F = c_f^2 a^2 V k (f1 + 3/2 f2) sin(2 k x) / (4 rho0)
+    with the measured amplitude a."""
+    import torch
+
+    from paper_1307_0702_amd import workloads as W
+    from paper_1307_0702_amd.ensemble import Ensemble
+
+    cases = W.force_sweeps_32()
+    ens = Ensemble([w for _, _, w in cases], prec="fp64", tune=False)
+    nT = cases[0][2].period_steps
+    assert nT % 3 == 0
+    chunk = nT // 3                          # steps per graph launch
+    nwarm = -(-nwarm // chunk) * chunk
+    t0 = time.perf_counter()
+    ens.capture(chunk)
+    log(f"[bench] force sweeps: {len(cases)} boxes, {nwarm} + {nper * nT} steps")
+    ens.run(nwarm // chunk)
+    for s_ in ens.sims:
+        s_.avg_force(reset=True)
+    ens.run(nper * nT // chunk)
+    forces = [s_.avg_force(reset=True)[0] for s_ in ens.sims]
+    a2 = np.zeros(len(cases))
+    for _ in range(3):
+        ens.run(1)
+        for i, (s_, (_, _, w)) in enumerate(zip(ens.sims, cases)):
+            d, _ = s_.get_state()
+            x = np.arange(w.fluid.nx) * w.fluid.h
+            c = np.cos(2 * math.pi * (x - w.modes[0].x0) / (w.fluid.nx * w.fluid.h))
+            a = 2.0 / w.fluid.nx * np.sum(d.mean(axis=(0, 1)) * c)
+            a2[i] += a * a / 3
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ens.release()
+    sweeps = {}
+    for (name, par, w), f, m2 in zip(cases, forces, a2):
+        fl, p = w.fluid, w.particles
+        V = 8.0 * fl.h ** 3
+        amp = math.sqrt(2.0 * m2)
+        k = 2 * math.pi / (fl.nx * fl.h)
+        f1 = 1.0 - p.kappa_ratio[0]
+        f2 = 2 * p.me[0] / (2 * p.me[0] + 3 * fl.rho0 * V)
+        x = (p.qeq[0, 0] - w.modes[0].x0) % (fl.nx * fl.h)
+        gork = fl.cf ** 2 * amp * amp * V * k / (4 * fl.rho0) * (f1 + 1.5 * f2) * math.sin(2 * k * x)
+        sweeps.setdefault(name, []).append(dict(
+            param=par, force=float(f[0, 0]), force_partner=float(f[1, 0]), gorkov=gork,
+            ratio=float(f[0, 0] / gork) if abs(gork) > 1e-18 else None, amplitude=amp))
+    steps = nwarm + nper * nT + nT
+    return dict(metric="radiation force sweeps against Gor'kov", value=len(cases) * 32 ** 3 * steps / wall,
+                unit="cell-updates/s", n_gpus=1, steps=steps, warmup=nwarm, ms_per_step=wall * 1e3 / steps,
+                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+                config=dict(workload="force-sweeps-32", boxes=len(cases), grid=[32, 32, 32], kT=0.0,
+                            eta=0.0125, amplitude=1e-3, average_periods=nper),
+                sweeps=sweeps)
+
+
 def run_force_precision(steps):
     """The paper-scale configuration with kT = 0 (256^3, 10^4 tethered
     particles of split contrast, standing wave of amplitude 1e-2): FP32
@@ -669,6 +731,9 @@ def main():
         return
     if args.workload == "gibbs-boltzmann":
         print(json.dumps(run_gibbs_boltzmann(args.steps, args.warmup)), flush=True)
+        return
+    if args.workload == "force-sweeps-32":
+        print(json.dumps(run_force_sweeps()), flush=True)
         return
     if args.workload == "force-precision-256":
         print(json.dumps(run_force_precision(args.steps)), flush=True)

@@ -310,6 +310,51 @@ def adjoint_64(n=16, seed=5, amp=2.3e-4):
     return Workload("adjoint-64", fl, p, modes, drho, g, nT)
 
 
+def force_pair_32(me, kappa_ratio, x, eta=0.0125, amp=1e-3, L=32):
+    """The radiation-force protocol of Sec. VI on an L^3 box in the paper's
+    low-viscosity regime: a resonant cosine drive along x (Delta rho = amp,
+    whole-step period), the fluid on the driven standing wave, and a
+    symmetric pair at x0 + x (y, z = L/2) and x0 - x (y, z = 0) with excess
+    mass me and kappa_p / kappa_f = kappa_ratio, softly tethered (k_s =
+    m_p (omega/6)^2).  Each particle starts where the fluid around it is at
+    t = 0, one end of its oscillation, so its mean position starts at the
+    anchor."""
+    fl = Fluid(L, L, L, kT=0.0, seed=1, eta=eta, zeta=eta)
+    mode, nT = modal_drive(fl, amp)
+    drho, g = standing_wave_fields(fl, amp, omega=mode.omega)
+    V = 8.0 * fl.h ** 3
+    Lx = fl.nx * fl.h
+    qeq = np.array([[(mode.x0 + x) % Lx, L / 2, L / 2], [(mode.x0 - x) % Lx, 0.0, 0.0]])
+    k = 2.0 * math.pi / Lx
+    kd = 2.0 / fl.h * math.sin(k * fl.h / 2.0)
+    q = qeq.copy()
+    q[:, 0] -= amp * np.sin(k * (qeq[:, 0] - mode.x0)) / kd
+    ks = (me + fl.rho0 * V) * (mode.omega / 6.0) ** 2
+    p = Particles(q=q, me=np.full(2, float(me)), kappa_ratio=np.full(2, float(kappa_ratio)),
+                  ks=np.full(2, ks), qeq=qeq)
+    return Workload("force-pair-32", fl, p, [mode], drho, g, nT)
+
+
+def force_sweeps_32():
+    """The sweeps behind the paper's force figures (Sec. VI), as a list of
+    (sweep, parameter, workload): the force along the wave for a dense
+    particle (m_e = rho0 V, kappa_p = kappa_f) and a stiff one (c_p = 2 c_f,
+    m_e = 0) at x = 2, 4, ..., 14 from the antinode (wavelength 32); and at
+    x = 4 (where sin 2kx = 1) the force against c_p / c_f for neutrally
+    buoyant particles and against rho_p / rho0 for particles as compressible
+    as the fluid."""
+    V = 8.0
+    out = []
+    for x in range(2, 16, 2):
+        out.append(("position-dipolar", float(x), force_pair_32(V, 1.0, float(x))))
+        out.append(("position-monopolar", float(x), force_pair_32(0.0, 0.25, float(x))))
+    for cr in (0.4, 0.6, 0.8, 1.25, 1.5, 2.0, 3.0):
+        out.append(("sound-speed-ratio", cr, force_pair_32(0.0, 1.0 / (cr * cr), 4.0)))
+    for dr in (0.5, 1.5, 2.0, 3.0, 5.0):
+        out.append(("density-ratio", dr, force_pair_32((dr - 1.0) * V, 1.0, 4.0)))
+    return out
+
+
 def ensemble(n=64, seed=4000, sizes=(32, 48, 64), max_particles=50, kT=1e-3):
     """n independent thermal replicas: grid edge drawn from `sizes`, 1 to
     max_particles free particles with m_p/(rho0 V) ~ U[0.5, 2] and

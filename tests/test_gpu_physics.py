@@ -335,3 +335,62 @@ def test_gibbs_boltzmann_position_distribution():
     assert abs(m - th) < 3 * max(se, 0.03)
     assert m < -0.1                      # well away from a uniform spread
 
+
+
+def test_force_sweeps_of_the_paper_figures_as_one_ensemble():
+    # Sec. VI force figures: the force along the wave for a dense particle
+    # (f2 = 0.4) and a stiff one (c_p = 2 c_f), and its maximum against
+    # c_p / c_f and rho_p / rho0 -- 26 boxes of 32^3 advanced together in
+    # HIP-graph launches (ensemble).  Gor'kov with the measured amplitude.
+    from paper_1307_0702_amd.ensemble import Ensemble
+    cases = W.force_sweeps_32()
+    ens = Ensemble([w for _, _, w in cases], prec="fp64", tune=False)
+    nT = cases[0][2].period_steps
+    chunk = nT // 3
+    ens.capture(chunk)
+    ens.run(-(-40000 // chunk))
+    for s in ens.sims:
+        s.avg_force(reset=True)
+    ens.run(8 * nT // chunk)
+    forces = [s.avg_force(reset=True)[0] for s in ens.sims]
+    a2 = np.zeros(len(cases))
+    for _ in range(3):                  # a third of a period apart: exact mean of a^2
+        ens.run(1)
+        for i, (s, (_, _, w)) in enumerate(zip(ens.sims, cases)):
+            d, _ = s.get_state()
+            x = np.arange(w.fluid.nx) * w.fluid.h
+            c = np.cos(2 * math.pi * (x - w.modes[0].x0) / (w.fluid.nx * w.fluid.h))
+            a = 2.0 / w.fluid.nx * np.sum(d.mean(axis=(0, 1)) * c)
+            a2[i] += a * a / 3
+    ens.release()
+    res = {}
+    for (name, par, w), f, m2 in zip(cases, forces, a2):
+        fl, p = w.fluid, w.particles
+        k = 2 * math.pi / (fl.nx * fl.h)
+        f1 = 1.0 - p.kappa_ratio[0]
+        f2 = 2 * p.me[0] / (2 * p.me[0] + 3 * fl.rho0 * V)
+        x = (p.qeq[0, 0] - w.modes[0].x0) % (fl.nx * fl.h)
+        gk = fl.cf ** 2 * 2 * m2 * V * k / (4 * fl.rho0) * (f1 + 1.5 * f2) * math.sin(2 * k * x)
+        res.setdefault(name, []).append((par, f[0, 0], gk))
+    scale = max(abs(f[0, 0]) for f in forces)
+    for f in forces:
+        assert abs(f[0, 0] + f[1, 0]) < 1e-6 * scale        # the mirrored pair's forces cancel
+    for name, rows in res.items():
+        print(f"  {name}: " + ", ".join(f"{par:g}: {fx / gk:.3f}" if abs(gk) > 1e-15 else f"{par:g}: node"
+                                       for par, fx, gk in rows), flush=True)
+    fmax = max(abs(fx) for _, fx, _ in res["position-dipolar"])
+    for name, lo, hi in (("position-dipolar", 0.94, 1.06), ("position-monopolar", 0.82, 0.95)):
+        for par, fx, gk in res[name]:
+            if par == 8.0:                    # the pressure node: sin 2kx = 0
+                assert abs(fx) < 0.03 * fmax, (name, fx)
+            else:
+                assert lo < fx / gk < hi, (name, par, fx / gk)
+    for par, fx, gk in res["sound-speed-ratio"]:
+        # soft particles (c_p < c_f) follow Gor'kov, stiff ones carry the
+        # monopolar deficit
+        lo, hi = (0.9, 1.1) if par < 1 else (0.78, 0.95)
+        assert lo < fx / gk < hi, (par, fx / gk)
+    soft = [abs(fx) for par, fx, _ in res["sound-speed-ratio"] if par < 1]
+    assert soft == sorted(soft, reverse=True)          # grows as c_p / c_f -> 0
+    for par, fx, gk in res["density-ratio"]:
+        assert 0.92 < fx / gk < 1.08, (par, fx / gk)
