@@ -241,6 +241,46 @@ def run_adjoint(prec, steps, warmup):
     return out
 
 
+def adjoint_step_cost(prec, nfwd=500, nrev=200):
+    """One reversed step with particles against one forward step on the
+    adjoint-64 workload (64^3, 16 tethered particles, four drives, kT = 0),
+    each timed over back-to-back steps: (forward ms, reversed ms)."""
+    import torch
+
+    from paper_1307_0702_amd import ic
+    from paper_1307_0702_amd.adjoint import Adjoint
+    from paper_1307_0702_amd.ic import Simulation
+
+    w = make_workload("adjoint-64")
+    fl, p = w.fluid, w.particles
+    sim = Simulation(fl, prec=prec, max_particles=p.n)
+    eps = np.array([ic.ic_eps_from_kappa_ratio(fl.cf, r) for r in p.kappa_ratio])
+    sim.set_particles(p.q, p.me, eps, ks=p.ks, qeq=p.qeq, fext=p.fext)
+    sim.set_forcing([m.as_dict() for m in w.modes])
+    adj = Adjoint(sim)
+    U, qs, us = adj.snapshot()
+    lam = torch.randn_like(sim.U)
+    lq = torch.randn((p.n, 3), dtype=torch.float64, device=sim.device)
+    lu = torch.randn_like(lq)
+    lF = torch.randn_like(lq)
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(k):
+            fn(i)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / k
+
+    timed(lambda i: sim.step(1), 50)
+    fwd = timed(lambda i: sim.step(1), nfwd)
+    timed(lambda i: adj.step(i, U, lam, qs, us, lq, lu, lF), 20)
+    rev = timed(lambda i: adj.step(i, U, lam, qs, us, lq, lu, lF), nrev)
+    del adj, sim
+    torch.cuda.empty_cache()
+    return fwd, rev
+
+
 def run_adjoint_particles(prec, periods, fd_check):
     """Reverse mode with particles: 64^3, kT = 0, 16 tethered particles, four
     resonant drives along x.  L = the x-component of the spring-force
@@ -273,24 +313,8 @@ def run_adjoint_particles(prec, periods, fd_check):
     ic.ic_copy_particles(sim.ctx, q0, u0)
     U0 = torch.zeros((4,) + sim.shape, dtype=sim.dtype, device=dev)
 
-    # one step each way, device-timed back to back
-    def timed(fn, k):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(k):
-            fn(i)
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3 / k
-
-    U, qs, us = adj.snapshot()
-    lam = torch.randn_like(sim.U)
-    lq = torch.randn((p.n, 3), dtype=torch.float64, device=dev)
-    lu = torch.randn_like(lq)
-    lF = torch.randn_like(lq)
-    timed(lambda i: sim.step(1), 50)
-    fwd = timed(lambda i: sim.step(1), 500)
-    timed(lambda i: adj.step(i, U, lam, qs, us, lq, lu, lF), 20)
-    rev = timed(lambda i: adj.step(i, U, lam, qs, us, lq, lu, lF), 200)
+    # one step each way, timed back to back on a context of its own
+    fwd, rev = adjoint_step_cost(prec)
 
     amps = torch.tensor([m["amp"] for m in md], dtype=torch.float64)
     me = torch.tensor(p.me, dtype=torch.float64)
@@ -702,6 +726,8 @@ def main():
     ap.add_argument("--periods", type=int, default=20,
                     help="adjoint-64: drive periods the loss averages over")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the reverse-mode step cost in the default line")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the graph-replayed step (a kernel trace then holds only the timed launches)")
     ap.add_argument("--copy-probe", action="store_true")
@@ -775,6 +801,15 @@ def main():
         graph_ms_per_step=r["graph_ms_per_step"],
         roofline=roofline(r, main_prec),
     )
+    if not args.no_adjoint:
+        # the reverse-mode cost of the metric: one reversed step with
+        # particles against one forward step (adjoint-64 workload)
+        adj = {}
+        for prec in precs:
+            f_ms, r_ms = adjoint_step_cost(prec)
+            adj[prec] = dict(forward_step_ms=f_ms, adjoint_step_ms=r_ms, ratio=r_ms / f_ms)
+            log(f"[bench] adjoint-64 {prec}: forward {f_ms:.3f} ms, reversed {r_ms:.3f} ms, ratio {r_ms / f_ms:.2f}")
+        out["adjoint"] = dict(workload="adjoint-64 (64^3, 16 tethered particles, four drives, kT = 0)", **adj)
     if "fp64" in res and main_prec != "fp64":
         r64 = res["fp64"]
         out["fp64"] = dict(value=r64["cell_updates_per_s"], ms_per_step=r64["ms_per_step"],
