@@ -29,6 +29,11 @@ Readings of points the paper leaves open (the spatial discretisation of the
 fluid solver is deferred by the paper to another reference) are marked
 "Reading:" in the code; each one is listed with its reason in the design
 notes of the repository.
+
+Parity unpinned: how the no-slip corrections of particles whose kernels
+overlap superpose (the Jacobi reading in ic_step) has no closed form or
+printed value to check it against; every other part of the step is pinned
+by the tests of the oracle.
 """
 from __future__ import annotations
 
