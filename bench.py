@@ -446,12 +446,14 @@ def run_force_sweeps(nwarm=40000, nper=8):
                 sweeps=sweeps)
 
 
-def run_force_precision(steps):
-    """The paper-scale configuration with kT = 0 (256^3, 10^4 tethered
-    particles of split contrast, standing wave of amplitude 1e-2): FP32
+def run_force_precision(steps, kT=0.0):
+    """The paper-scale configuration (256^3, 10^4 tethered particles of split
+    contrast, standing wave of amplitude 1e-2) with kT = 0 by default: FP32
     (fields as deviations from rho0, FP64 particles and accumulators) against
     all-FP64, the spring-force estimator of the radiation force averaged over
-    the last 7 whole drive periods of `steps` steps, and the FP32 speed-up."""
+    the last 7 whole drive periods of `steps` steps, and the FP32 speed-up.
+    With kT > 0 both runs draw the same noise (same Philox streams), and the
+    difference is that of two thermal trajectories from the same start."""
     import torch
 
     from paper_1307_0702_amd import ic
@@ -459,7 +461,7 @@ def run_force_precision(steps):
 
     w = make_workload("paper-scale-256")
     fl, p = w.fluid, w.particles
-    fl.kT = 0.0
+    fl.kT = kT
     nT = w.period_steps
     navg = 7 * nT
     nwarm = max(steps - navg, 0)
@@ -489,8 +491,9 @@ def run_force_precision(steps):
                 value=t64 / t32, unit="x", n_gpus=1, steps=nwarm + navg, warmup=0,
                 ms_per_step=t32 * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
                 dtype="f32", data="synthetic",
-                config=dict(workload="paper-scale-256-kT0", grid=[fl.nx, fl.ny, fl.nz],
-                            particles=p.n, kT=0.0, averaged_steps=ns, period_steps=nT),
+                config=dict(workload="paper-scale-256-kT0" if kT == 0 else "paper-scale-256",
+                            grid=[fl.nx, fl.ny, fl.nz], particles=p.n, kT=kT, averaged_steps=ns,
+                            period_steps=nT),
                 fp64_ms_per_step=t64 * 1e3, force_rel_err_max=rel_max, force_rel_err_rms=rel_rms,
                 mean_abs_force_fp64=float(np.mean(np.abs(f64))))
 
@@ -763,6 +766,9 @@ def main():
         return
     if args.workload == "force-precision-256":
         print(json.dumps(run_force_precision(args.steps)), flush=True)
+        return
+    if args.workload == "force-precision-256-thermal":
+        print(json.dumps(run_force_precision(args.steps, kT=1e-3)), flush=True)
         return
     if args.workload == "adjoint-64":
         for prec in (["fp32", "fp64"] if args.prec == "both" else [args.prec]):
