@@ -156,7 +156,7 @@ def run_gpu(w, prec, steps, warmup, graph=True):
 def run_ensemble(prec, steps, warmup):
     """64 thermal replicas (grid edges 32/48/64, 1-50 particles, own seeds and
     replica ids): aggregate cell-updates/s of member-after-member eager steps
-    and of one HIP-graph launch per `steps` steps of all members."""
+    and of HIP-graph launches of all members (one launch per 50 steps)."""
     import torch
 
     from paper_1307_0702_amd import workloads as W
@@ -172,11 +172,14 @@ def run_ensemble(prec, steps, warmup):
     ens.run_serial(steps)
     ens.synchronize()
     t_serial = time.perf_counter() - t0
-    ens.capture(steps)
+    # 50-step graphs replayed: measured 2.37e9 cell-updates/s against 1.75e9
+    # for one 200-step graph (FP32, 4 hardware queues; more queues were slower)
+    chunk = 50 if steps % 50 == 0 else steps
+    ens.capture(chunk)
     ens.run()
     ens.synchronize()
     t0 = time.perf_counter()
-    ens.run()
+    ens.run(steps // chunk)
     ens.synchronize()
     t_graph = time.perf_counter() - t0
     tiles = {}
@@ -191,6 +194,16 @@ def run_ensemble(prec, steps, warmup):
                            tile_z_by_edge=tiles),
                serial_value=cells * steps / t_serial,
                graph_speedup=t_serial / t_graph)
+    # whole-step roofline of the graph launch: the stage kernels' 32 words
+    # per cell-update over the replayed steps, against the HBM peak (the
+    # replicas' 8.2e6 cells take 131 MB per FP32 state copy and about 1 GB
+    # with the stage copies and noise fields, beyond the 256 MB last-level
+    # cache, so HBM is the bound that applies)
+    esz = 4 if prec == "fp32" else 8
+    gbs = cells * steps * WORDS_PER_CELL_UPDATE * esz / t_graph / 1e9
+    out["roofline"] = dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                           frac=gbs / HBM_PEAK_GBS, traffic=None, kernel="whole step (graph replay)",
+                           bytes_per_cell_update=WORDS_PER_CELL_UPDATE * esz)
     ens.release()
     del ens
     torch.cuda.empty_cache()
