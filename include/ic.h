@@ -155,12 +155,14 @@ int ic_get_tile(ic_ctx *ctx, int32_t *tz);
 int ic_step(ic_ctx *ctx, int64_t nsteps);
 
 /* Averaging operator J (Sec. II, Eq. Jdis; staggered positions of App. A):
- * out[p] = sum_i h^3 theta_h(q_p - r_i) field[i] for n positions q ([n][3],
- * device) and a field of the given location kind (device, context
- * precision, nx*ny*nz).  out is device, double[n].  With kind IC_FACES,
+ * out[p] = sum_i h^3 theta_h(q_p - r_i) field[i] for n positions q ([n][3])
+ * and a field of the given location kind (device, context precision,
+ * nx*ny*nz).  out is double[n].  With kind IC_FACES,
  * field holds the x, y and z face components one after another (3 nx*ny*nz,
  * e.g. the momentum of a state) and out is double[n][3], the averaged
- * vector J_alpha f^alpha.  Asynchronous. */
+ * vector J_alpha f^alpha.  Asynchronous when q and out are device memory;
+ * either may instead be host memory (detected), and then the call stages
+ * them through a temporary device buffer and synchronises. */
 int ic_interpolate(ic_ctx *ctx, int32_t n, const double *q, int32_t kind,
                    const void *field, double *out);
 

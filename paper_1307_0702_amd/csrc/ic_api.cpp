@@ -501,6 +501,16 @@ int ic_step(ic_ctx *c, int64_t nsteps) {
     return IC_OK;
 }
 
+// True when p is device memory the kernels can read and write directly.
+static bool is_device_pointer(const void *p) {
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();   // unregistered host memory reports an error
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
 int ic_interpolate(ic_ctx *c, int32_t n, const double *q, int32_t kind, const void *field,
                    double *out) {
     if (!c) return IC_E_ARG;
@@ -508,8 +518,30 @@ int ic_interpolate(ic_ctx *c, int32_t n, const double *q, int32_t kind, const vo
     if (kind < IC_CELL || kind > IC_FACES) return fail(c, IC_E_ARG, "bad kind");
     if (n == 0) return IC_OK;
     if (!q || !field || !out) return fail(c, IC_E_ARG, "NULL pointer");
-    hipError_t e = launch_interpolate(c, n, q, kind, field, out);
-    if (e != hipSuccess) return hip_fail(c, e, "interpolate launch");
+    const bool q_dev = is_device_pointer(q), out_dev = is_device_pointer(out);
+    if (q_dev && out_dev) {
+        hipError_t e = launch_interpolate(c, n, q, kind, field, out);
+        if (e != hipSuccess) return hip_fail(c, e, "interpolate launch");
+        return IC_OK;
+    }
+    // host positions or results: staged through one device buffer
+    const size_t nq = 3 * (size_t)n, no = (kind == IC_FACES ? 3 : 1) * (size_t)n;
+    double *tmp = nullptr;
+    hipError_t e = hipMalloc((void **)&tmp, (nq + no) * sizeof(double));
+    if (e != hipSuccess) return hip_fail(c, e, "interpolate staging");
+    const double *qd = q;
+    double *od = out_dev ? out : tmp + nq;
+    if (!q_dev) {
+        e = hipMemcpyAsync(tmp, q, nq * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        qd = tmp;
+    }
+    if (e == hipSuccess) e = launch_interpolate(c, n, qd, kind, field, od);
+    if (e == hipSuccess && !out_dev)
+        e = hipMemcpyAsync(out, od, no * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    const hipError_t ef = hipFree(tmp);
+    if (e == hipSuccess) e = ef;
+    if (e != hipSuccess) return hip_fail(c, e, "interpolate");
     return IC_OK;
 }
 

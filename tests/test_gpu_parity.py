@@ -215,6 +215,16 @@ def test_interpolate_faces_is_the_three_face_kernels():
         assert np.array_equal(got[:, a], one)
         want = O.interpolate(g[a].astype(np.float64), q, fl.h, a)
         assert _rel(got[:, a], want) < 1e-13
+    # host positions and a host result: staged by the library, same values
+    import torch
+    gd = torch.as_tensor(g, device=sim.device).contiguous()
+    qh = np.ascontiguousarray(q)
+    out_h = np.zeros((40, 3))
+    ic.ic_interpolate(sim.ctx, 40, qh, ic.IC_FACES, gd, out_h)
+    assert np.array_equal(out_h, got)
+    out_h1 = np.zeros(40)
+    ic.ic_interpolate(sim.ctx, 40, torch.as_tensor(qh, device=sim.device), ic.IC_FACE_Y, gd[1], out_h1)
+    assert np.array_equal(out_h1, got[:, 1])
 
 
 def test_get_and_set_state_resume_bit_for_bit():
