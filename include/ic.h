@@ -238,7 +238,9 @@ int ic_graph_destroy(ic_graph *graph);
  * of the context precision, IC_MAX_MODES doubles per 256 cells and 18
  * doubles per particle of max_particles).
  * ic_bind_adjoint: binds it (caller-owned, 256-byte aligned) and zeroes the
- * drive-gradient accumulator.  Synchronising.
+ * drive-gradient accumulator.  Synchronising.  workspace = NULL with
+ * bytes = 0 unbinds it (before the caller frees it); the adjoint calls then
+ * return IC_E_STATE until a workspace is bound again.
  * ic_adjoint_step: for step n taken from the state U^n = (drho, gx, gy, gz)
  * (device, context precision, nx*ny*nz each, read only), replaces the adjoint
  * (ldrho, lgx, lgy, lgz) = dL/dU^{n+1} (device, same layout) by dL/dU^n and

@@ -34,6 +34,16 @@ class Adjoint:
             self.ws = self._raw[off:off + nbytes]
             ic.ic_bind_adjoint(sim.ctx, self.ws, nbytes)
 
+    def __del__(self):
+        # the context must not keep pointers into the workspace torch frees
+        sim = getattr(self, "sim", None)
+        if sim is not None and getattr(sim, "ctx", None) is not None:
+            try:
+                sim.synchronize()
+                ic.ic_bind_adjoint(sim.ctx, None, 0)
+            except Exception:
+                pass
+
     def step(self, n, U, lam, q=None, u=None, lq=None, lu=None, lF=None):
         """lam := dL/dU^n from lam = dL/dU^{n+1}; U = U^n (4 device fields).
         With particles set, also q, u = the particle state of step n and

@@ -643,6 +643,11 @@ int ic_adjoint_workspace_size(const ic_params *p, size_t *bytes) {
 
 int ic_bind_adjoint(ic_ctx *c, void *workspace, size_t bytes) {
     if (!c) return IC_E_ARG;
+    if (!workspace && bytes == 0) {   // unbind: the caller is about to free it
+        c->adj_bound = false;
+        c->adj = AdjWorkspace{};
+        return IC_OK;
+    }
     if (!workspace) return fail(c, IC_E_ARG, "NULL adjoint workspace");
     if (((uintptr_t)workspace & 255) != 0) return fail(c, IC_E_ARG, "adjoint workspace not 256-byte aligned");
     if (bytes < adjoint_workspace_bytes(c->p)) return fail(c, IC_E_ARG, "adjoint workspace too small");

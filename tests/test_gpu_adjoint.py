@@ -188,3 +188,19 @@ def test_adjoint_error_paths():
     with pytest.raises(ic.ICError) as e:
         ic.ic_bind_adjoint(sim.ctx, adj.ws, 16)
     assert e.value.code == ic.IC_E_ARG
+
+
+def test_workspace_is_unbound_when_the_adjoint_object_goes():
+    import gc
+    from paper_1307_0702_amd import ic
+    from paper_1307_0702_amd.adjoint import Adjoint
+    from paper_1307_0702_amd.ic import Simulation
+    sim = Simulation(W.Fluid(16, 16, 16, kT=0.0, seed=4), prec="fp64")
+    U, lam = sim.U.clone(), sim.U.clone()
+    adj = Adjoint(sim)
+    adj.step(0, U, lam)
+    del adj
+    gc.collect()
+    with pytest.raises(ic.ICError) as e:
+        ic.ic_adjoint_step(sim.ctx, 0, list(U), list(lam))
+    assert e.value.code == ic.IC_E_STATE and "not bound" in str(e.value)
