@@ -60,7 +60,8 @@ enum { IC_MAX_MODES = 8 };
  * (0 switches the stochastic stress off), dt time step.  seed keys the
  * Philox generator; replica is its fourth counter word (independent
  * realisations of one seed).  prec is IC_FP32 or IC_FP64.  max_particles
- * bounds the particle count of ic_set_particles/ic_interpolate/ic_spread. */
+ * bounds the particle count of ic_set_particles and ic_spread and sizes the
+ * per-particle parts of both workspaces (ic_interpolate takes any n). */
 typedef struct ic_params {
     int32_t nx, ny, nz;
     int32_t prec;
