@@ -58,6 +58,7 @@ if ROOT not in sys.path:
 METRIC = "cell-updates/s + % HBM roofline at 256^3/1e4 particles; FP32 vs FP64; adjoint cost"
 HBM_PEAK_GBS = 8000.0
 WORDS_PER_CELL_UPDATE = 32          # over the three stage launches of one step
+ADJ_WORDS_PER_CELL = 72             # one reversed step (recomputation included)
 STAGES = 3
 KERNEL_SRC = os.path.join(ROOT, "paper_1307_0702_amd", "csrc", "ic_device.hip")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "stage_kernel_256cube_1e4p_pmc.txt")
@@ -242,12 +243,22 @@ def run_adjoint(prec, steps, warmup):
     timed(lambda i: adj.step(i, U, lam), warmup)
     rev = timed(lambda i: adj.step(i, U, lam), steps)
     ncell = fl.nx * fl.ny * fl.nz
+    # algorithmic traffic of one reversed step: the two recomputed forward
+    # stages (8 + 12 words per cell) and the three transposed stages, each
+    # reading its input state and incoming adjoint and writing its outgoing
+    # adjoint, with the accumulator written (third), read and written
+    # (second) or read (first): 16 + 20 + 16 words -- 72 words per cell
+    esz = 4 if prec == "fp32" else 8
+    gbs = ADJ_WORDS_PER_CELL * esz * ncell / (rev * 1e-3) / 1e9
     out = dict(metric="adjoint cell-updates/s", value=ncell / (rev * 1e-3), unit="cell-updates/s",
                n_gpus=1, steps=steps, warmup=warmup, ms_per_step=rev, higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="f32" if prec == "fp32" else "f64",
                data="synthetic",
                config=dict(workload="adjoint-256", grid=[fl.nx, fl.ny, fl.nz], particles=0, kT=0.0),
                forward_ms_per_step=fwd, adjoint_over_forward=rev / fwd,
+               roofline=dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                             frac=gbs / HBM_PEAK_GBS, traffic=None, kernel="whole reversed step",
+                             bytes_per_cell=ADJ_WORDS_PER_CELL * esz),
                finite=bool(torch.isfinite(lam).all()))
     del adj, sim
     torch.cuda.empty_cache()
