@@ -1270,6 +1270,118 @@ __global__ __launch_bounds__(64) void k_bin_sort(const BinArgs b) {
     }
 }
 
+// Binning of a small particle set (at most SB_CAP particles, so no tile
+// list exceeds SB_CAP entries, and at most SB_MAXBLK tiles) in one
+// workgroup: counts and cursors in LDS, the exclusive scan as in k_bin_scan,
+// then each wave sorts and colours whole tile lists exactly as k_bin_sort
+// does.  One launch instead of four: on small grids the binning sits on the
+// step's critical path, where launch latency dominates it.
+constexpr int SB_THREADS = 1024, SB_WAVES = SB_THREADS / 64;
+constexpr int SB_CAP = 128;
+constexpr int SB_MAXBLK = 4096;
+
+// LDS written by some lanes of a wave, read by others after this point
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(SB_THREADS) void k_bin_small(const BinArgs b) {
+    __shared__ int32_t s_cur[SB_MAXBLK];
+    __shared__ int32_t s_part[SB_THREADS];
+    __shared__ int32_t w_q[SB_WAVES][SB_CAP], w_p[SB_WAVES][SB_CAP], w_c[SB_WAVES][SB_CAP];
+    __shared__ int32_t w_b[SB_WAVES][SB_CAP][3];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nblk = b.nblk;
+    for (int i = tid; i < nblk; i += SB_THREADS) s_cur[i] = 0;
+    __syncthreads();
+    for (int p = tid; p < b.np; p += SB_THREADS) {
+        int bl[27];
+        const int n = particle_blocks(b, p, bl);
+        for (int c = 0; c < n; ++c) atomicAdd(&s_cur[bl[c]], 1);
+    }
+    __syncthreads();
+    // exclusive scan of the counts: offsets to memory, cursors in LDS
+    const int chunk = (nblk + SB_THREADS - 1) / SB_THREADS;
+    const int lo = min(tid * chunk, nblk), hi = min(lo + chunk, nblk);
+    int sum = 0;
+    for (int i = lo; i < hi; ++i) sum += s_cur[i];
+    s_part[tid] = sum;
+    __syncthreads();
+    for (int o = 1; o < SB_THREADS; o <<= 1) {
+        const int v = tid >= o ? s_part[tid - o] : 0;
+        __syncthreads();
+        s_part[tid] += v;
+        __syncthreads();
+    }
+    int run = s_part[tid] - sum;
+    for (int i = lo; i < hi; ++i) {
+        const int cnt = s_cur[i];
+        b.off[i] = run;
+        s_cur[i] = run;
+        run += cnt;
+    }
+    if (tid == SB_THREADS - 1) b.off[nblk] = s_part[SB_THREADS - 1];
+    __syncthreads();
+    for (int p = tid; p < b.np; p += SB_THREADS) {
+        int bl[27];
+        const int n = particle_blocks(b, p, bl);
+        for (int c = 0; c < n; ++c) b.list[atomicAdd(&s_cur[bl[c]], 1)] = p;
+    }
+    __syncthreads();
+    // each wave: whole tile lists, sorted by id, coloured greedily, ordered
+    // by (colour, id)
+    const int nn[3] = {b.nx, b.ny, b.nz};
+    int32_t *sq = w_q[wave], *sp = w_p[wave], *sc = w_c[wave];
+    int32_t(*sb)[3] = w_b[wave];
+    for (int blk = wave; blk < nblk; blk += SB_WAVES) {
+        const int s0 = b.off[blk], n = b.off[blk + 1] - s0;
+        if (n == 0) continue;
+        for (int i = lane; i < n; i += 64) sq[i] = b.list[s0 + i];
+        wave_lds_sync();
+        for (int i = lane; i < n; i += 64) {
+            const int pi = sq[i];
+            int rank = 0;
+            for (int j = 0; j < n; ++j) rank += sq[j] < pi;
+            sp[rank] = pi;
+        }
+        wave_lds_sync();
+        for (int i = lane; i < n; i += 64) {
+            const int pi = sp[i];
+            sb[i][0] = b.bc[3 * pi];
+            sb[i][1] = b.bc[3 * pi + 1];
+            sb[i][2] = b.bc[3 * pi + 2];
+        }
+        wave_lds_sync();
+        for (int i = 0; i < n; ++i) {
+            unsigned long long used = 0;
+            int far = 0;
+            for (int j = lane; j < i; j += 64) {
+                if (boxes_overlap(sb[i], sb[j], nn)) {
+                    if (sc[j] < 64) used |= 1ull << sc[j];
+                    else far = max(far, sc[j] + 1);
+                }
+            }
+            for (int o = 32; o >= 1; o >>= 1) {
+                used |= __shfl_xor(used, o, 64);
+                far = max(far, __shfl_xor(far, o, 64));
+            }
+            const int c = ~used ? __builtin_ctzll(~used) : max(64, far);
+            if (lane == 0) sc[i] = c;
+            wave_lds_sync();
+        }
+        for (int i = lane; i < n; i += 64) {
+            const int ci = sc[i];
+            int rank = 0;
+            for (int j = 0; j < n; ++j) rank += sc[j] < ci || (sc[j] == ci && j < i);
+            b.list[s0 + rank] = sp[i];
+            b.key[s0 + rank] = ci;
+        }
+        wave_lds_sync();   // before the wave's next list reuses its buffers
+    }
+}
+
 // Sparse owner-computes updates of the grid near particles, one stage block
 // per workgroup.  The block's candidates arrive ordered by (colour, id) from
 // k_bin_sort; candidates of one colour touch disjoint points, so each colour
@@ -2187,6 +2299,10 @@ inline unsigned thread_blocks(int n) { return (unsigned)((n + 255) / 256); }
 
 void launch_binning(ic_ctx *c, int np, const double *qh, hipStream_t s) {
     const BinArgs b = bin_args(c, np, qh);
+    if (np <= SB_CAP && b.nblk <= SB_MAXBLK) {
+        hipLaunchKernelGGL(k_bin_small, dim3(1), dim3(SB_THREADS), 0, s, b);
+        return;
+    }
     hipLaunchKernelGGL(k_bin_count, dim3(thread_blocks(np)), dim3(256), 0, s, b);
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, b);
     hipLaunchKernelGGL(k_bin_fill, dim3(thread_blocks(np)), dim3(256), 0, s, b);
