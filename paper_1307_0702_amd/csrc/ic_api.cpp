@@ -68,7 +68,7 @@ static size_t layout(const ic_params &p, char *base, Workspace *ws) {
     auto d1 = [&]() { return (double *)take(N * sizeof(double)); };
     w.q = d3(); w.u = d3(); w.me = d1(); w.eps = d1(); w.ks = d1(); w.qeq = d3(); w.fext = d3();
     w.qh = d3(); w.jv_old = d3(); w.F = d3(); w.Vt = d3(); w.du = d3(); w.mf = d3();
-    w.omega = d1(); w.jv_new = d3();
+    w.omega = (double *)take(2 * N * sizeof(double)); w.jv_new = d3();   // two stages' Omega
     w.pk.bc = (int32_t *)take(3 * N * sizeof(int32_t));
     w.pk.bf = (int32_t *)take(3 * N * sizeof(int32_t));
     w.pk.wc = (double *)take(9 * N * sizeof(double));

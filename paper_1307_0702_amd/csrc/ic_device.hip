@@ -1403,6 +1403,13 @@ struct SparseArgs {
     const double *wc, *wf;
     const double *val;   // SPREAD: f[p]; NOSLIP: du[p][3]; STAGE: F[p][3]
     const double *omega; // STAGE only
+    // STAGE only, optional: Omega of the next stage, eps V J(drho_next) with
+    // drho_next the density this stage wrote, computed by the block whose
+    // tile holds the particle's nearest cell (nullptr: not computed)
+    double *omega_next;
+    const T *drho_next;
+    const double *eps;
+    double V;
     int kind;            // SPREAD only
     T *fields[3];
     const T *drho;       // NOSLIP only
@@ -1414,7 +1421,7 @@ constexpr int SP_BATCH = 4;   // items per thread whose loads are issued togethe
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(SP_THREADS) void k_sparse(const SparseArgs<T> a) {
-    __shared__ int32_t s_bc[SP_CAP][3], s_bf[SP_CAP][3], s_col[SP_CAP];
+    __shared__ int32_t s_bc[SP_CAP][3], s_bf[SP_CAP][3], s_col[SP_CAP], s_pid[SP_CAP];
     __shared__ double s_wc[SP_CAP][9], s_wf[SP_CAP][9], s_v[SP_CAP][4];
     const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     const int cb = a.blk_off[blk], ce = a.blk_off[blk + 1];
@@ -1434,6 +1441,7 @@ __global__ __launch_bounds__(SP_THREADS) void k_sparse(const SparseArgs<T> a) {
         __syncthreads();
         for (int i = tid; i < nc; i += SP_THREADS) {
             const int pid = a.blk_list[c0 + i];
+            s_pid[i] = pid;
             s_col[i] = a.blk_color[c0 + i];
             for (int d = 0; d < 3; ++d) {
                 s_bc[i][d] = a.bc[3 * pid + d];
@@ -1551,6 +1559,33 @@ __global__ __launch_bounds__(SP_THREADS) void k_sparse(const SparseArgs<T> a) {
             }
             __syncthreads();
             r0 = r1;
+        }
+        if (MODE == SP_STAGE && a.omega_next) {
+            // Omega of the next stage for the candidates whose nearest cell
+            // is in this tile (one block per particle), one wave each: the
+            // same 27 products and butterfly sum as k_omega
+            const int lane = tid & 63, wave = tid >> 6;
+            int owned = 0;
+            for (int i = 0; i < nc; ++i) {
+                bool mine = true;
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    const int cc = wrap(s_bc[i][ax] + 1, n[ax]);
+                    mine = mine && cc >= lo[ax] && cc < lo[ax] + wd[ax];
+                }
+                if (!mine) continue;
+                if (owned++ % (SP_THREADS / 64) != wave) continue;
+                double v = 0.0;
+                if (lane < 27) {
+                    const int d0 = lane % 3, d1 = (lane / 3) % 3, d2 = lane / 9;
+                    const int x = wrap(s_bc[i][0] + d0, nx), y = wrap(s_bc[i][1] + d1, ny),
+                              z = wrap(s_bc[i][2] + d2, nz);
+                    const double w = s_wc[i][d0] * s_wc[i][3 + d1] * s_wc[i][6 + d2];
+                    v = w * (double)a.drho_next[((size_t)z * ny + y) * nx + x];
+                }
+                v = wave_sum(v);
+                if (lane == 0) a.omega_next[s_pid[i]] = a.eps[s_pid[i]] * a.V * v;
+            }
         }
     }
 }
@@ -2424,10 +2459,20 @@ hipError_t step_impl(ic_ctx *c, bool overlap, bool first, bool last) {
     void *const B[4] = {w.B[0], w.B[1], w.B[2], w.B[3]};
     void *const *src[3] = {U, A, B};
     void *const *dst[3] = {A, B, U};
+    // Omega of stage st lives in omega[st & 1] (k_pre writes stage 0's).
+    // Unless the next step's noise runs beside this step, the sparse pass
+    // after stage st also computes stage st + 1's into the other half (two
+    // launches fewer per step); beside that noise, separate k_omega launches
+    // measured faster, as the noise kernel then overlaps them rather than
+    // the stage kernels.
+    const size_t ostride = (size_t)(p.max_particles > 0 ? p.max_particles : 0);
+    const bool fuse_omega = !ahead;
     for (int st = 0; st < 3; ++st) {
-        if (np > 0 && st > 0)
+        if (np > 0 && st > 0 && !fuse_omega) {
+            pa.omega = w.omega + (st & 1) * ostride;
             hipLaunchKernelGGL(k_omega<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa,
                                (const T *)src[st][0]);
+        }
         for (int i = 0; i < 4; ++i) {
             a.in[i] = (const T *)src[st][i];
             a.un[i] = (const T *)U[i];
@@ -2464,7 +2509,13 @@ hipError_t step_impl(ic_ctx *c, bool overlap, bool first, bool last) {
             SparseArgs<T> sa = sparse_args<T>(c);
             sa.b = rb[st];
             sa.val = w.F;
-            sa.omega = w.omega;
+            sa.omega = w.omega + (st & 1) * ostride;
+            if (fuse_omega && st < 2) {
+                sa.omega_next = w.omega + ((st + 1) & 1) * ostride;
+                sa.drho_next = (const T *)dst[st][0];
+                sa.eps = w.eps;
+                sa.V = 8.0 * p.h * p.h * p.h;
+            }
             for (int i = 0; i < 3; ++i) sa.fields[i] = (T *)dst[st][1 + i];
             hipLaunchKernelGGL((k_sparse<T, SP_STAGE>), grid, dim3(SP_THREADS), 0, s, sa);
         }

@@ -57,7 +57,8 @@ struct Workspace {
     void *N[2][9];
     // persistent particle state, [N][3] or [N]
     double *q, *u, *me, *eps, *ks, *qeq, *fext;
-    // per-step particle data
+    // per-step particle data (omega: [2][N], the Omega of two consecutive
+    // RK stages)
     double *qh, *jv_old, *F, *Vt, *du, *mf, *omega, *jv_new;
     PartKernel pk;
     // binning of particles into stage blocks
