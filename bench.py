@@ -547,10 +547,12 @@ def run_gibbs_boltzmann(steps, warmup):
     sim.step(warmup)
     ph = []
     every = 200
-    for _ in range(steps // every):
+    for i in range(steps // every):
         sim.step(every)
         q, _ = sim.get_particles()
         ph.append((2 * k * (q[:, 0] - mode.x0)) % (2 * math.pi))
+        if (i + 1) % 500 == 0:
+            log(f"[bench] gibbs-boltzmann: {(i + 1) * every} of {steps} steps")
     wall = time.perf_counter() - t0
     # amplitude of the driven density mode over one period
     x = np.arange(fl.nx) * fl.h
