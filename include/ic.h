@@ -167,6 +167,28 @@ int ic_step(ic_ctx *ctx, int64_t nsteps);
 int ic_interpolate(ic_ctx *ctx, int32_t n, const double *q, int32_t kind,
                    const void *field, double *out);
 
+/* Largest n of ic_interpolate_noalloc. */
+enum { IC_NOALLOC_MAX_POINTS = 16384 };
+
+/* ic_interpolate for callers that cannot allocate device memory (serving
+ * loops and harnesses that forbid hipMalloc): the same averaging J, the same
+ * arguments and the same results, bit for bit, as ic_interpolate, but host
+ * positions or results are staged through a static device buffer of the
+ * library instead of a temporary allocation; no hipMalloc, hipFree or other
+ * allocating call is made.  The buffer holds 6 * IC_NOALLOC_MAX_POINTS
+ * doubles (768 KiB) on each GPU the library runs on, kept until the process
+ * ends; its device address is looked up on the first staged call on a GPU.
+ * IC_E_ARG when n > IC_NOALLOC_MAX_POINTS (also with device arrays).  With q
+ * and out both in device memory nothing is staged and the call is
+ * asynchronous, as ic_interpolate; otherwise it synchronises the context
+ * stream.  Every context on one GPU shares that GPU's buffer: the library
+ * holds a per-GPU lock from the first copy to the final synchronisation, so
+ * staged calls of one process never overlap (calls from several threads
+ * wait for each other).  The buffer keeps the last call's contents; nothing
+ * in it needs to start at zero. */
+int ic_interpolate_noalloc(ic_ctx *ctx, int32_t n, const double *q, int32_t kind,
+                           const void *field, double *out);
+
 /* Spreading operator S (Sec. II, Eq. Sdis): adds theta_h(q_p - r_i) f[p] to
  * field[i] for every p, so sum_i h^3 field[i] grows by sum_p f[p].  q
  * ([n][3]) and f (double[n]) are device arrays; field is device (context

@@ -545,6 +545,27 @@ int ic_interpolate(ic_ctx *c, int32_t n, const double *q, int32_t kind, const vo
     return IC_OK;
 }
 
+int ic_interpolate_noalloc(ic_ctx *c, int32_t n, const double *q, int32_t kind,
+                           const void *field, double *out) {
+    if (!c) return IC_E_ARG;
+    if (n < 0) return fail(c, IC_E_ARG, "n < 0");
+    if (n > IC_NOALLOC_MAX_POINTS)
+        return fail(c, IC_E_ARG,
+                    "n > IC_NOALLOC_MAX_POINTS: the static staging buffer of "
+                    "ic_interpolate_noalloc holds 16384 positions (use ic_interpolate)");
+    if (kind < IC_CELL || kind > IC_FACES) return fail(c, IC_E_ARG, "bad kind");
+    if (n == 0) return IC_OK;
+    if (!q || !field || !out) return fail(c, IC_E_ARG, "NULL pointer");
+    const bool q_dev = is_device_pointer(q), out_dev = is_device_pointer(out);
+    hipError_t e;
+    if (q_dev && out_dev)
+        e = launch_interpolate(c, n, q, kind, field, out);
+    else
+        e = launch_interpolate_noalloc(c, n, q, q_dev, kind, field, out, out_dev);
+    if (e != hipSuccess) return hip_fail(c, e, "interpolate (no allocation)");
+    return IC_OK;
+}
+
 int ic_spread(ic_ctx *c, int32_t n, const double *q, const double *f, int32_t kind, void *field) {
     int rc = check_bound(c);
     if (rc != IC_OK) return rc;

@@ -20,6 +20,7 @@
 // results are bitwise reproducible.
 #include <math.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "ic_internal.h"
@@ -2848,6 +2849,65 @@ hipError_t launch_conserved(ic_ctx *c, double *host_out) {
 hipError_t launch_set_step(ic_ctx *c) {
     hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, c->stream, c->ws.st, (int64_t)c->step);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Staging memory of ic_interpolate_noalloc: a file-scope device array (one
+// copy on every GPU the library runs on, held until the process ends) in
+// place of the temporary allocation of ic_interpolate.  In host code the
+// array's name is only a host-side stand-in, never a device address: the
+// address is looked up once per GPU with hipGetSymbolAddress, with that GPU
+// current, and only the looked-up pointer is passed to copies and kernels.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t SCRATCH_DOUBLES = 6 * (size_t)IC_NOALLOC_MAX_POINTS;  // [n][3] q + [n][3] out
+__device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;                              // guards the lookup table
+std::mutex scratch_use[SCRATCH_MAX_DEVICES];        // one staged call per GPU at a time
+double *scratch_ptr[SCRATCH_MAX_DEVICES];
+
+hipError_t scratch_address(int device, double **out) {
+    *out = nullptr;
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != device) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        scratch_ptr[device] = (double *)ptr;
+    }
+    *out = scratch_ptr[device];
+    return hipSuccess;
+}
+}  // namespace
+
+hipError_t launch_interpolate_noalloc(ic_ctx *c, int n, const double *q, bool q_dev, int kind,
+                                      const void *field, double *out, bool out_dev) {
+    if (n > IC_NOALLOC_MAX_POINTS) return hipErrorInvalidValue;
+    double *scr = nullptr;
+    hipError_t e = scratch_address(c->device, &scr);
+    if (e != hipSuccess) return e;
+    const size_t nq = 3 * (size_t)n, no = (kind == IC_FACES ? 3 : 1) * (size_t)n;
+    std::lock_guard<std::mutex> lk(scratch_use[c->device]);
+    const double *qd = q_dev ? q : scr;
+    double *od = out_dev ? out : scr + 3 * (size_t)IC_NOALLOC_MAX_POINTS;
+    if (!q_dev) e = hipMemcpyAsync(scr, q, nq * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_interpolate(c, n, qd, kind, field, od);
+    if (e == hipSuccess && !out_dev)
+        e = hipMemcpyAsync(out, od, no * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    // the staging memory is free for the next call once the stream is idle
+    const hipError_t es = hipStreamSynchronize(c->stream);
+    return e != hipSuccess ? e : es;
 }
 
 }  // namespace ic

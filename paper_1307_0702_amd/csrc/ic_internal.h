@@ -178,6 +178,11 @@ int nblocks_of(const ic_ctx *c);            // at the context's z extent
 hipError_t launch_step(ic_ctx *c, bool overlap, bool first, bool last);
 hipError_t launch_interpolate(ic_ctx *c, int n, const double *q, int kind, const void *field,
                               double *out);
+// ic_interpolate_noalloc: positions / results in host memory (flags false)
+// are staged through the library's static device buffer; synchronises the
+// context stream.  n <= IC_NOALLOC_MAX_POINTS.
+hipError_t launch_interpolate_noalloc(ic_ctx *c, int n, const double *q, bool q_dev, int kind,
+                                      const void *field, double *out, bool out_dev);
 hipError_t launch_spread(ic_ctx *c, int n, const double *q, const double *f, int kind,
                          void *field);
 hipError_t launch_init_velocity(ic_ctx *c);

@@ -21,11 +21,12 @@ IC_FP32, IC_FP64 = 1, 2
 IC_CELL, IC_FACE_X, IC_FACE_Y, IC_FACE_Z, IC_FACES = 0, 1, 2, 3, 4
 IC_MODE_COS, IC_MODE_PLANE = 0, 1
 IC_MAX_MODES = 8
+IC_NOALLOC_MAX_POINTS = 16384
 
 EXPORTED = [
     "ic_create", "ic_destroy", "ic_workspace_size", "ic_bind", "ic_set_particles",
     "ic_get_particles", "ic_set_forcing", "ic_set_step", "ic_get_step", "ic_step",
-    "ic_interpolate", "ic_spread", "ic_avg_force", "ic_conserved",
+    "ic_interpolate", "ic_interpolate_noalloc", "ic_spread", "ic_avg_force", "ic_conserved",
     "ic_eps_from_kappa_ratio", "ic_strerror", "ic_last_error", "ic_profile", "ic_profile_read",
     "ic_set_tile", "ic_get_tile", "ic_graph_create", "ic_graph_launch", "ic_graph_destroy",
     "ic_adjoint_workspace_size", "ic_bind_adjoint", "ic_adjoint_step", "ic_adjoint_drive",
@@ -75,6 +76,7 @@ def load_library(path=LIB_PATH):
         "ic_get_step": ([P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "ic_step": ([P, ctypes.c_int64], ctypes.c_int),
         "ic_interpolate": ([P, ctypes.c_int32, P, ctypes.c_int32, P, P], ctypes.c_int),
+        "ic_interpolate_noalloc": ([P, ctypes.c_int32, P, ctypes.c_int32, P, P], ctypes.c_int),
         "ic_spread": ([P, ctypes.c_int32, P, P, ctypes.c_int32, P], ctypes.c_int),
         "ic_avg_force": ([P, P, P, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32], ctypes.c_int),
         "ic_conserved": ([P, dp], ctypes.c_int),
@@ -271,6 +273,13 @@ def ic_load_particles(ctx, q_dev, u_dev):
 
 def ic_interpolate(ctx, n, q_dev, kind, field_dev, out_dev):
     _check(_lib.ic_interpolate(ctx, int(n), _ptr(q_dev), int(kind), _ptr(field_dev), _ptr(out_dev)), ctx)
+
+
+def ic_interpolate_noalloc(ctx, n, q, kind, field_dev, out):
+    """q ([n][3] float64) and out (float64 [n], or [n][3] for IC_FACES):
+    host numpy arrays or device tensors; field_dev: a device tensor."""
+    _check(_lib.ic_interpolate_noalloc(ctx, int(n), _ptr(q), int(kind), _ptr(field_dev), _ptr(out)),
+           ctx)
 
 
 def ic_spread(ctx, n, q_dev, f_dev, kind, field_dev):
