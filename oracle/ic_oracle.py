@@ -32,8 +32,9 @@ notes of the repository.
 
 Parity unpinned: how the no-slip corrections of particles whose kernels
 overlap superpose (the Jacobi reading in ic_step) has no closed form or
-printed value to check it against; every other part of the step is pinned
-by the tests of the oracle.
+printed value to check it against beyond what stays exact with overlap (total
+momentum conservation and the fluid-force identity of lambda, both pinned);
+every other part of the step is pinned by the tests of the oracle.
 """
 from __future__ import annotations
 
