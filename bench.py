@@ -622,6 +622,48 @@ def roofline(r, prec):
                 if traffic else None)
 
 
+def host_cpu():
+    """CPU model and the number of cores this process may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return model, n
+
+
+def run_table1(log_fn):
+    """Table I (Sec. VI) in the paper's units: the driven density amplitude
+    of each force figure without particles against the printed value, and
+    the symmetric pair's mean spring force against Gor'kov's."""
+    from paper_1307_0702_amd.experiments import table1_run
+
+    rows = {}
+    for fig in ("force", "force3"):
+        r0 = table1_run(fig, particles=False, log=log_fn)
+        r1 = table1_run(fig, particles=True, log=log_fn)
+        rows[fig] = dict(drho_measured=r0["amp"], drho_printed=r0["printed"],
+                         drho_rel_err=r0["amp"] / r0["printed"] - 1,
+                         force_x=r1["force"][:, 0].tolist(), gorkov_x=r1["gorkov"].tolist(),
+                         ratio=(r1["force"][:, 0] / r1["gorkov"]).tolist(),
+                         drho_with_particles=r1["amp"])
+        log_fn(f"[bench] table I {fig}: drho {r0['amp']:.6e} vs printed {r0['printed']:.6e}; "
+               f"F/F_Gorkov {rows[fig]['ratio']}")
+    return dict(metric="Table I: driven density amplitude and radiation force in the paper's units",
+                value=rows["force3"]["drho_rel_err"], unit="relative error of drho (Fig. force3)",
+                higher_is_better=False, n_gpus=1, dtype="f64", data="synthetic",
+                config=dict(workload="table1", grid=[32, 32, 32], h=10.0, cf=4.0, eta=0.5,
+                            drive="Kronecker plane, 0.005"),
+                figures=rows)
+
+
 def cpu_baseline(w):
     """One FP64 oracle step of the full workload (same fields, particles,
     drive and noise key) on the host."""
@@ -639,10 +681,12 @@ def cpu_baseline(w):
     cpu = time.process_time() - c0
     ncell = fl.nx * fl.ny * fl.nz
     log(f"[bench] cpu baseline: {wall:.1f} s")
+    model, ncores = host_cpu()
     return dict(value=ncell / wall, unit="cell-updates/s", cores=max(1, int(round(cpu / wall))),
                 kind="oracle",
                 sample=f"1 FP64 oracle step (numpy, as it stands) of the full workload: "
-                       f"{fl.nx}x{fl.ny}x{fl.nz} cells, {p.n} particles; {wall:.1f} s wall")
+                       f"{fl.nx}x{fl.ny}x{fl.nz} cells, {p.n} particles; {wall:.1f} s wall",
+                cpu_model=model, host_cores_available=ncores)
 
 
 def copy_probe():
@@ -759,6 +803,10 @@ def main():
                     help="skip the reverse-mode step cost in the default line")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the graph-replayed step (a kernel trace then holds only the timed launches)")
+    ap.add_argument("--no-force-precision", action="store_true",
+                    help="skip the FP32-against-FP64 averaged-force leg of the default line")
+    ap.add_argument("--force-steps", type=int, default=20000,
+                    help="steps of each run of the averaged-force precision leg")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--stats-summary", metavar="CSV")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"))
@@ -789,6 +837,20 @@ def main():
         return
     if args.workload == "force-sweeps-32":
         print(json.dumps(run_force_sweeps()), flush=True)
+        return
+    if args.workload == "table1":
+        print(json.dumps(run_table1(log)), flush=True)
+        return
+    if args.workload == "gorkov-single-32":
+        from paper_1307_0702_amd.experiments import gorkov_single_32
+        r = gorkov_single_32()
+        log(f"[bench] one particle, eta = zeta = 0.5: F_x {r['force'][0]:.4e}, Gor'kov "
+            f"{r['gorkov']:.4e}, ratio {r['ratio']:.3f}")
+        print(json.dumps(dict(metric="averaged spring force against Gor'kov, one particle",
+                              value=r["ratio"], unit="F / F_Gorkov", n_gpus=1, dtype="f64",
+                              data="synthetic", higher_is_better=False,
+                              config=dict(workload="gorkov-single-32", grid=[32, 32, 32], eta=0.5,
+                                          zeta=0.5, particles=1, steps=1000), **r)), flush=True)
         return
     if args.workload == "force-precision-256":
         print(json.dumps(run_force_precision(args.steps)), flush=True)
@@ -848,6 +910,18 @@ def main():
                            roofline=roofline(r64, "fp64"))
         out["speedup_fp32_over_fp64"] = r["cell_updates_per_s"] / r64["cell_updates_per_s"]
     out["finite"] = all(x["finite"] for x in res.values())
+    if not args.no_force_precision and w.name == "paper-scale-256":
+        # the metric's precision claim: FP32 against FP64 on this
+        # configuration at kT = 0, averaged spring forces over 7 periods
+        fp = run_force_precision(args.force_steps)
+        out["force_precision"] = dict(
+            workload="paper-scale-256 at kT = 0", steps=fp["steps"],
+            averaged_steps=fp["config"]["averaged_steps"],
+            force_rel_err_max=fp["force_rel_err_max"], force_rel_err_rms=fp["force_rel_err_rms"],
+            fp32_ms_per_step=fp["ms_per_step"], fp64_ms_per_step=fp["fp64_ms_per_step"],
+            speedup_fp32_over_fp64=fp["value"])
+        log(f"[bench] force precision: rel err {fp['force_rel_err_max']:.2e} (max), "
+            f"speed-up {fp['value']:.2f}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -198,8 +198,16 @@ def rollout_particles(adj, U0, q0, u0, amps, me, eps, modes, n0, nsteps, every=6
                 sim.set_forcing(md)
                 ks_, qeq_, fext_ = fixed_
                 q_host = q0_.detach().cpu().numpy()
-                sim.set_particles(q_host, me_.detach().numpy(), eps_.detach().numpy(),
-                                  u=u0_.detach().cpu().numpy(), ks=ks_, qeq=qeq_, fext=fext_)
+                u_host = u0_.detach().cpu().numpy()
+                me_h, eps_h = me_.detach().numpy().copy(), eps_.detach().numpy().copy()
+                sim.set_particles(q_host, me_h, eps_h, u=u_host, ks=ks_, qeq=qeq_, fext=fext_)
+                # the particle set and parameters of this trajectory: backward
+                # re-steps and reverses with them, whatever the shared context
+                # holds by then (another rollout may have run in between)
+                ctx.particles = (q_host, me_h, eps_h, u_host,
+                                 None if ks_ is None else np.array(ks_, dtype=np.float64),
+                                 None if qeq_ is None else np.array(qeq_, dtype=np.float64),
+                                 None if fext_ is None else np.array(fext_, dtype=np.float64))
                 UN, ck = adj_.forward(U0_.detach(), n0_, nsteps_, every_, q0_.detach(), u0_.detach())
                 tether, _, _ = sim.avg_force(reset=True)   # mean of k_s minimg(q^{n+1/2} - q_eq)
                 f0 = np.zeros((sim.np, 3)) if fext_ is None else np.asarray(fext_, dtype=np.float64)
@@ -213,6 +221,8 @@ def rollout_particles(adj, U0, q0, u0, amps, me, eps, modes, n0, nsteps, every=6
             def backward(ctx, gU, gq, gu, gF):
                 a = ctx.adj
                 sim = a.sim
+                q_h, me_h, eps_h, u_h, ks_h, qeq_h, fext_h = ctx.particles
+                sim.set_particles(q_h, me_h, eps_h, u=u_h, ks=ks_h, qeq=qeq_h, fext=fext_h)
                 a.sim.set_forcing(ctx.md)
                 a.drive_grad(len(ctx.md), reset=True)
                 a.particle_grad(reset=True)

@@ -78,6 +78,10 @@ static size_t layout(const ic_params &p, char *base, Workspace *ws) {
     w.blk_cursor = (int32_t *)take((nblk + 1) * sizeof(int32_t));
     w.blk_list = (int32_t *)take(N * MAX_BLOCKS_PER_PARTICLE * sizeof(int32_t));
     w.blk_key = (int32_t *)take(N * MAX_BLOCKS_PER_PARTICLE * sizeof(int32_t));
+    auto i1 = [&]() { return (int32_t *)take(N * sizeof(int32_t)); };
+    w.cl_parent = i1(); w.cl_root = i1(); w.cl_cnt = i1();
+    w.cl_off = (int32_t *)take((N + 1) * sizeof(int32_t));
+    w.cl_cursor = i1(); w.cl_list = i1();
     w.sum_f = d3(); w.sum_l = d3();
     w.prof = (double *)take((size_t)IC_MAX_MODES * pmax * sizeof(double));
     w.red = (double *)take(4 * 1024 * sizeof(double));
@@ -190,17 +194,22 @@ int check_bound(ic_ctx *c) {
 }
 
 // Device flags: [0] a step found m_e + m_f <= 0, [1] a reversed step got a
-// non-finite particle position.
+// non-finite particle position, [2] a step met a non-finite particle
+// position, velocity or impulse (a NaN or inf in the fields or particles).
 int take_flag(ic_ctx *c) {
-    int32_t flag[2] = {0, 0};
+    int32_t flag[3] = {0, 0, 0};
     hipError_t e = hipMemcpyAsync(flag, c->ws.flag, sizeof(flag), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "flag readback");
-    if (flag[0] || flag[1]) {
-        const int32_t zero[2] = {0, 0};
+    if (flag[0] || flag[1] || flag[2]) {
+        const int32_t zero[3] = {0, 0, 0};
         e = hipMemcpyAsync(c->ws.flag, zero, sizeof(zero), hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "flag reset");
+        if (flag[2])
+            return fail(c, IC_E_ARG,
+                        "non-finite state: a step met a non-finite particle position, velocity "
+                        "or impulse (NaN or inf in the fields or particles)");
         if (flag[0]) return fail(c, IC_E_MASS, "a step found m_e + m_f <= 0");
         return fail(c, IC_E_ARG, "a reversed step got a non-finite particle position");
     }

@@ -925,12 +925,29 @@ __global__ __launch_bounds__(256) void k_pre(const PartArgs<T> a) {
     const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (p >= a.np) return;
     const int lane = threadIdx.x & 63;
-    const double q[3] = {a.q[3 * p], a.q[3 * p + 1], a.q[3 * p + 2]};
+    double q[3] = {a.q[3 * p], a.q[3 * p + 1], a.q[3 * p + 2]};
+    // A non-finite position or velocity (NaN or inf in the fields) would
+    // reach the integer point indices of the kernel: it is replaced by 0 and
+    // reported through flag[2].
+    bool bad = false;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax)
+        if (!isfinite(q[ax])) {
+            bad = true;
+            q[ax] = 0.0;
+        }
     double U[3];
     wave_face_sums<T>(a.G, a.f, q, U, nullptr);           // J^n v^n at q^n
     double qh[3];
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) qh[ax] = wrap_pos(q[ax] + 0.5 * a.dt * U[ax], a.L[ax]);
+    for (int ax = 0; ax < 3; ++ax) {
+        qh[ax] = wrap_pos(q[ax] + 0.5 * a.dt * U[ax], a.L[ax]);
+        if (!isfinite(qh[ax])) {
+            bad = true;
+            qh[ax] = 0.0;
+        }
+    }
+    if (bad && lane == 0) a.flag[2] = 1;
     double jv[3];
     wave_face_sums<T>(a.G, a.f, qh, jv, nullptr);         // J^{n+1/2} v^n
     const WaveKernel k = wave_kernel(a.G, qh);
@@ -1031,29 +1048,6 @@ __global__ __launch_bounds__(256) void k_post(const PartArgs<T> a) {
     }
 }
 
-// Substep 7 and the window sums: q^{n+1} = q^n + dt/2 J^{n+1/2}(v^{n+1}+v^n).
-template <typename T>
-__global__ __launch_bounds__(256) void k_final(const PartArgs<T> a) {
-    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (p >= a.np) return;
-    const int lane = threadIdx.x & 63;
-    const double qh[3] = {a.qh[3 * p], a.qh[3 * p + 1], a.qh[3 * p + 2]};
-    double jv[3];
-    wave_face_sums<T>(a.G, a.f, qh, jv, nullptr);
-    if (lane < 3) {
-        const int ax = lane;
-        const double q = a.q[3 * p + ax];
-        a.q[3 * p + ax] = wrap_pos(q + 0.5 * a.dt * (jv[ax] + a.jv_old[3 * p + ax]), a.L[ax]);
-        const double un = a.Vt[3 * p + ax];
-        const double F = a.F[3 * p + ax];
-        const double lam = a.me[p] * (un - a.u[3 * p + ax]) / a.dt - F;
-        a.sum_f[3 * p + ax] += -(F - a.fext[3 * p + ax]);
-        a.sum_l[3 * p + ax] += lam;
-        a.u[3 * p + ax] = un;
-        a.jv_new[3 * p + ax] = jv[ax];
-    }
-}
-
 // u := J v at the particle positions (no-slip initial velocity).
 template <typename T>
 __global__ __launch_bounds__(256) void k_init_u(const PartArgs<T> a) {
@@ -1074,8 +1068,12 @@ __global__ __launch_bounds__(256) void k_interp(const Grid G, int np, const doub
     if (p >= np) return;
     const int lane = threadIdx.x & 63;
     const double L[3] = {G.nx * G.h, G.ny * G.h, G.nz * G.h};
-    const double qq[3] = {wrap_pos(q[3 * p], L[0]), wrap_pos(q[3 * p + 1], L[1]),
-                          wrap_pos(q[3 * p + 2], L[2])};
+    double qq[3] = {wrap_pos(q[3 * p], L[0]), wrap_pos(q[3 * p + 1], L[1]),
+                    wrap_pos(q[3 * p + 2], L[2])};
+    // a non-finite position gives NaN (it never reaches the point indices)
+    const bool bad = !(isfinite(qq[0]) && isfinite(qq[1]) && isfinite(qq[2]));
+    if (bad) qq[0] = qq[1] = qq[2] = 0.0;
+    const double nan_or_0 = bad ? __builtin_nan("") : 0.0;
     const WaveKernel k = wave_kernel(G, qq);
     if (kind != IC_FACES) {
         size_t i;
@@ -1083,7 +1081,7 @@ __global__ __launch_bounds__(256) void k_interp(const Grid G, int np, const doub
         wave_point(G, k, kind, lane < 27 ? lane : 0, &i, &w);
         double s = lane < 27 ? w * (double)field[i] : 0.0;
         s = wave_sum(s);
-        if (lane == 0) out[p] = s;
+        if (lane == 0) out[p] = s + nan_or_0;
         return;
     }
     // three consecutive face fields (x, y, z components), out [n][3]
@@ -1095,7 +1093,7 @@ __global__ __launch_bounds__(256) void k_interp(const Grid G, int np, const doub
         wave_point(G, k, 1 + ax, lane < 27 ? lane : 0, &i, &w);
         double s = lane < 27 ? w * (double)field[ax * ncell + i] : 0.0;
         s = wave_sum(s);
-        if (lane == 0) out[3 * p + ax] = s;
+        if (lane == 0) out[3 * p + ax] = s + nan_or_0;
     }
 }
 
@@ -1588,6 +1586,517 @@ __global__ __launch_bounds__(SP_THREADS) void k_sparse(const SparseArgs<T> a) {
                 if (lane == 0) a.omega_next[s_pid[i]] = a.eps[s_pid[i]] * a.V * v;
             }
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Particle clusters of one step.  A cluster is a connected component of the
+// graph that joins two particles when their influence boxes intersect (the
+// 4 x 4 x 4 points [bc-1, bc+2] per axis that a particle's stage terms,
+// no-slip correction and gathers reach).  Particles of different clusters
+// touch disjoint grid points, so one wave per cluster can update the grid
+// with plain read-modify-writes; inside a cluster the wave takes its members
+// one after another in ascending id, so every point receives its sums in the
+// same order on every run (no float atomics).  Most clusters hold one
+// particle.
+// Union-find: parent[p] is p or a smaller id; a union hooks the larger root
+// onto the smaller one with a compare-and-swap, so the root of a component
+// is its smallest id whatever order the unions run in.
+// ---------------------------------------------------------------------------
+struct ClusterArgs {
+    int np;
+    int32_t *parent;   // union-find forest
+    int32_t *root;     // root of each particle
+    int32_t *cnt;      // members of the cluster whose root is p (0 for non-roots)
+    int32_t *off;      // exclusive prefix sums of cnt ([np + 1])
+    int32_t *cursor;   // fill cursors
+    int32_t *list;     // members grouped by root, in fill order
+};
+
+__device__ __forceinline__ int uf_find(int32_t *parent, int x) {
+    for (;;) {
+        const int p = __hip_atomic_load(parent + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (p == x) return x;
+        x = p;
+    }
+}
+
+__device__ __forceinline__ void uf_union(int32_t *parent, int a, int b) {
+    for (;;) {
+        a = uf_find(parent, a);
+        b = uf_find(parent, b);
+        if (a == b) return;
+        if (a < b) {
+            const int t = a;
+            a = b;
+            b = t;
+        }
+        int expected = a;
+        if (__hip_atomic_compare_exchange_strong(parent + a, &expected, b, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            return;
+    }
+}
+
+// One wave per tile list: unions of the listed particles whose influence
+// boxes intersect.  Every point of a particle's box lies in a tile the
+// particle is listed for, so two intersecting boxes share the tile of a
+// common point and every edge of the graph is seen.  Lists longer than
+// UNION_CAP are merged whole: a cluster larger than needed is still
+// processed correctly, only more serially.
+constexpr int UNION_CAP = 256;
+
+__global__ __launch_bounds__(64) void k_bin_union(const BinArgs b, int32_t *parent) {
+    __shared__ int32_t s_id[UNION_CAP], s_b[UNION_CAP][3];
+    const int blk = blockIdx.x, lane = threadIdx.x;
+    const int s0 = b.off[blk], n = b.off[blk + 1] - s0;
+    if (n <= 1) return;
+    if (n > UNION_CAP) {
+        for (int i = 1 + lane; i < n; i += 64) uf_union(parent, b.list[s0], b.list[s0 + i]);
+        return;
+    }
+    for (int i = lane; i < n; i += 64) {
+        const int p = b.list[s0 + i];
+        s_id[i] = p;
+        s_b[i][0] = b.bc[3 * p];
+        s_b[i][1] = b.bc[3 * p + 1];
+        s_b[i][2] = b.bc[3 * p + 2];
+    }
+    __syncthreads();
+    const int nn[3] = {b.nx, b.ny, b.nz};
+    for (int i = 1; i < n; ++i)
+        for (int j = lane; j < i; j += 64)
+            if (boxes_overlap(s_b[i], s_b[j], nn)) uf_union(parent, s_id[i], s_id[j]);
+}
+
+// parent[p] = p, cnt[p] = 0 (before the unions of a step)
+__global__ __launch_bounds__(256) void k_cl_init(const ClusterArgs a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.np) return;
+    a.parent[p] = p;
+    a.cnt[p] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_cl_count(const ClusterArgs a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.np) return;
+    const int r = uf_find(a.parent, p);
+    a.root[p] = r;
+    atomicAdd(a.cnt + r, 1);
+}
+
+// Exclusive scan of cnt into off and cursor (one workgroup).
+__global__ __launch_bounds__(1024) void k_cl_scan(const ClusterArgs a) {
+    __shared__ int32_t part[1024];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int chunk = (a.np + nt - 1) / nt;
+    const int lo = min(tid * chunk, a.np), hi = min(lo + chunk, a.np);
+    int s = 0;
+    for (int i = lo; i < hi; ++i) s += a.cnt[i];
+    part[tid] = s;
+    __syncthreads();
+    for (int o = 1; o < nt; o <<= 1) {
+        const int v = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int run = part[tid] - s;
+    for (int i = lo; i < hi; ++i) {
+        a.off[i] = run;
+        a.cursor[i] = run;
+        run += a.cnt[i];
+    }
+    if (tid == nt - 1) a.off[a.np] = part[nt - 1];
+}
+
+__global__ __launch_bounds__(256) void k_cl_fill(const ClusterArgs a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.np) return;
+    a.list[atomicAdd(a.cursor + a.root[p], 1)] = p;
+}
+
+// Clusters of at most CL_SMALL_CAP particles in one workgroup: every pair
+// tested directly, the forest and the counts in LDS, then the same root,
+// cnt, off and list arrays as the general path (members of a cluster listed
+// in ascending id).  One launch instead of seven on small particle sets.
+constexpr int CL_SMALL_CAP = 512;
+
+__global__ __launch_bounds__(1024) void k_cl_small(const ClusterArgs a, const int32_t *bc, int nx,
+                                                   int ny, int nz) {
+    __shared__ int32_t s_par[CL_SMALL_CAP], s_b[CL_SMALL_CAP][3], s_cnt[CL_SMALL_CAP + 1];
+    const int tid = threadIdx.x, np = a.np;
+    const int nn[3] = {nx, ny, nz};
+    for (int p = tid; p < np; p += blockDim.x) {
+        s_par[p] = p;
+        s_cnt[p] = 0;
+        s_b[p][0] = bc[3 * p];
+        s_b[p][1] = bc[3 * p + 1];
+        s_b[p][2] = bc[3 * p + 2];
+    }
+    __syncthreads();
+    // hook each particle onto the smallest overlapping id below it, then
+    // take minima along the chains until nothing changes (a component's root
+    // is its smallest id, as in the general path)
+    for (int p = tid; p < np; p += blockDim.x) {
+        int m = p;
+        for (int q = 0; q < p; ++q)
+            if (boxes_overlap(s_b[p], s_b[q], nn)) {
+                m = q;
+                break;
+            }
+        s_par[p] = m;
+    }
+    __syncthreads();
+    // min-label propagation over the edges: repeat until stable
+    __shared__ int changed;
+    for (;;) {
+        if (tid == 0) changed = 0;
+        __syncthreads();
+        for (int p = tid; p < np; p += blockDim.x) {
+            int m = s_par[s_par[p]];
+            for (int q = 0; q < np; ++q)
+                if (q != p && boxes_overlap(s_b[p], s_b[q], nn)) m = min(m, s_par[q]);
+            if (m < s_par[p]) {
+                s_par[p] = m;
+                changed = 1;
+            }
+        }
+        __syncthreads();
+        if (!changed) break;
+        __syncthreads();
+    }
+    for (int p = tid; p < np; p += blockDim.x) {
+        a.root[p] = s_par[p];
+        atomicAdd(&s_cnt[s_par[p]], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int p = 0; p < np; ++p) {
+            const int c = s_cnt[p];
+            a.off[p] = run;
+            a.cnt[p] = c;
+            s_cnt[p] = run;
+            run += c;
+        }
+        a.off[np] = run;
+        // members in ascending id: one pass in id order
+        for (int p = 0; p < np; ++p) a.list[s_cnt[s_par[p]]++] = p;
+    }
+}
+
+// Next member above `last` of the cluster list[o, o + k) (its smallest id
+// greater than last).
+__device__ __forceinline__ int cluster_next(const int32_t *list, int o, int k, int last) {
+    const int lane = threadIdx.x & 63;
+    int best = 0x7fffffff;
+    for (int i = lane; i < k; i += 64) {
+        const int v = list[o + i];
+        if (v > last && v < best) best = v;
+    }
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) best = min(best, __shfl_xor(best, s, 64));
+    return best;
+}
+
+// A wave's view of one particle's kernel data: lanes 0..8 the cell
+// weights wc[axis][point], lanes 9..17 the face weights, lanes 18..20 the
+// first cell index and 21..23 the first face index per axis.
+struct WaveStencil {
+    double w;
+    int i;
+};
+
+__device__ __forceinline__ WaveStencil load_stencil(const int32_t *bc, const int32_t *bf,
+                                                    const double *wc, const double *wf, int p) {
+    const int lane = threadIdx.x & 63;
+    WaveStencil s{0.0, 0};
+    if (lane < 9)
+        s.w = wc[9 * p + lane];
+    else if (lane < 18)
+        s.w = wf[9 * p + lane - 9];
+    else if (lane < 21)
+        s.i = bc[3 * p + lane - 18];
+    else if (lane < 24)
+        s.i = bf[3 * p + lane - 21];
+    return s;
+}
+__device__ __forceinline__ double st_wc(const WaveStencil &s, int ax, int d) {
+    return __shfl(s.w, 3 * ax + d, 64);
+}
+__device__ __forceinline__ double st_wf(const WaveStencil &s, int ax, int d) {
+    return __shfl(s.w, 9 + 3 * ax + d, 64);
+}
+__device__ __forceinline__ int st_bc(const WaveStencil &s, int ax) { return __shfl(s.i, 18 + ax, 64); }
+__device__ __forceinline__ int st_bf(const WaveStencil &s, int ax) { return __shfl(s.i, 21 + ax, 64); }
+
+// Grid updates of one particle become visible to the next member's loads
+// (same wave, same workgroup).
+__device__ __forceinline__ void member_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Stage terms of one RK stage (App. A, stage pressures; reading R18): for
+// each particle, g^a += b [-(dt/h) (P(i+a) - P(i)) + dt F^a w_a / h^3] with
+// P = Omega w / h^3, over the 4 x 3 x 3 faces of each component its pressure
+// and force reach; and the next stage's Omega = eps V J(drho_next) from the
+// density this stage wrote (the same 27 products and butterfly as k_omega).
+template <typename T>
+struct StagePassArgs {
+    int nx, ny, nz, np;
+    double inv_h3, b, dt_h, dt, V;
+    const int32_t *root, *cnt, *off, *list;
+    const int32_t *bc, *bf;
+    const double *wc, *wf;
+    const double *F, *omega, *eps;
+    double *omega_next;   // nullptr after the last stage
+    const T *drho_next;
+    T *g[3];
+};
+
+template <typename T>
+__device__ __forceinline__ void stage_terms_of(const StagePassArgs<T> &a, int p) {
+    const int lane = threadIdx.x & 63;
+    const int n[3] = {a.nx, a.ny, a.nz};
+    const WaveStencil s = load_stencil(a.bc, a.bf, a.wc, a.wf, p);
+    const double om = a.omega[p];
+    const double Fp[3] = {a.F[3 * p], a.F[3 * p + 1], a.F[3 * p + 2]};
+    int bcv[3], sh[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        bcv[ax] = st_bc(s, ax);
+        int d = bcv[ax] - st_bf(s, ax);   // 0 or 1 up to the period
+        if (d < 0) d += n[ax];
+        sh[ax] = d;
+    }
+    size_t gi[2];
+    double add[2];
+    int cmp[2];
+    bool ok[2];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const int item = lane + 64 * it;
+        ok[it] = item < 108;
+        const int itm = ok[it] ? item : 0;
+        const int fa = itm / 36, pt = itm - 36 * fa;
+        int d[3];
+        if (fa == 0) {
+            d[0] = pt % 4; d[1] = (pt / 4) % 3; d[2] = pt / 12;
+        } else if (fa == 1) {
+            d[0] = pt % 3; d[1] = (pt / 3) % 4; d[2] = pt / 12;
+        } else {
+            d[0] = pt % 3; d[1] = (pt / 3) % 3; d[2] = pt / 9;
+        }
+        int pos[3];
+        double po = 1.0;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            pos[ax] = wrap(bcv[ax] - (ax == fa ? 1 : 0) + d[ax], n[ax]);
+            // every lane takes part in the shuffles; the face axis reads
+            // point 0 and does not use it
+            const double wv = st_wc(s, ax, ax == fa ? 0 : d[ax]);
+            if (ax != fa) po *= wv;
+        }
+        const int dc = d[fa];
+        const int of = dc - 1 + sh[fa];
+        const double wpos = st_wc(s, fa, dc >= 1 ? dc - 1 : 0);
+        const double wnb = st_wc(s, fa, dc <= 2 ? dc : 2);
+        const double wff = st_wf(s, fa, (of >= 0 && of <= 2) ? of : 0);
+        const double w_pos = dc >= 1 ? po * wpos : 0.0;
+        const double w_nb = dc <= 2 ? po * wnb : 0.0;
+        const double w_f = (of >= 0 && of <= 2) ? po * wff : 0.0;
+        const double dP = om * (w_nb - w_pos) * a.inv_h3;
+        const double fw = Fp[fa] * w_f * a.inv_h3;
+        gi[it] = ((size_t)pos[2] * a.ny + pos[1]) * a.nx + pos[0];
+        add[it] = a.b * (-a.dt_h * dP + a.dt * fw);
+        cmp[it] = fa;
+    }
+    T old[2];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) old[it] = ok[it] ? a.g[cmp[it]][gi[it]] : (T)0;
+#pragma unroll
+    for (int it = 0; it < 2; ++it)
+        if (ok[it]) a.g[cmp[it]][gi[it]] = (T)((double)old[it] + add[it]);
+    if (a.omega_next) {
+        double v = 0.0;
+        const int l27 = lane < 27 ? lane : 0;
+        const int d0 = l27 % 3, d1 = (l27 / 3) % 3, d2 = l27 / 9;
+        const double w = st_wc(s, 0, d0) * st_wc(s, 1, d1) * st_wc(s, 2, d2);
+        if (lane < 27) {
+            const int x = wrap(bcv[0] + d0, a.nx), y = wrap(bcv[1] + d1, a.ny),
+                      z = wrap(bcv[2] + d2, a.nz);
+            v = w * (double)a.drho_next[((size_t)z * a.ny + y) * a.nx + x];
+        }
+        v = wave_sum(v);
+        if (lane == 0) a.omega_next[p] = a.eps[p] * a.V * v;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cl_stage(const StagePassArgs<T> a) {
+    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (p >= a.np || a.root[p] != p) return;
+    const int k = a.cnt[p];
+    if (k == 1) {
+        stage_terms_of(a, p);
+        return;
+    }
+    const int o = a.off[p];
+    int m = p;   // the root is the cluster's smallest id
+    for (int i = 0; i < k; ++i) {
+        if (i) {
+            member_fence();
+            m = cluster_next(a.list, o, k, m);
+        }
+        stage_terms_of(a, m);
+    }
+}
+
+// Substeps 4-7 for one cluster per wave (App. A): the impulse and particle
+// velocity of every member from the unconstrained state (as k_post), then
+// the momentum-conserving corrections member after member (as k_sparse in
+// no-slip mode), then the full-step positions q^{n+1} = q^n + dt/2
+// J^{n+1/2}(v^{n+1} + v^n) and the window sums from the corrected state.
+// Reading R6: every member's V~ comes from the uncorrected state.  A non-finite V~, m_f or position raises flag[2]
+// (and the position keeps its old value); m_e + m_f <= 0 raises flag[0].
+template <typename T>
+struct PostPassArgs {
+    PartArgs<T> pa;
+    const int32_t *root, *cnt, *off, *list;
+    T *g[3];        // momentum of U^{n+1}, corrected in place
+    double inv_h3;
+};
+
+template <typename T>
+__device__ __forceinline__ void impulse_of(const PartArgs<T> &a, int p) {
+    const int lane = threadIdx.x & 63;
+    const double qh[3] = {a.qh[3 * p], a.qh[3 * p + 1], a.qh[3 * p + 2]};
+    double Vt[3], sm[3];
+    wave_face_sums<T>(a.G, a.f, qh, Vt, sm);
+    if (lane < 3) {
+        const int ax = lane;
+        const double me = a.me[p];
+        const double mf = a.V * sm[ax];
+        const double u = a.u[3 * p + ax];
+        double un = u + mf / (me + mf) * (Vt[ax] - u);
+        double du = a.V * (un - Vt[ax]);
+        if (!isfinite(Vt[ax]) || !isfinite(mf)) {
+            a.flag[2] = 1;
+            un = u;
+            du = 0.0;
+        } else if (!(me + mf > 0.0)) {
+            a.flag[0] = 1;
+        }
+        a.Vt[3 * p + ax] = un;  // u^{n+1}
+        a.du[3 * p + ax] = du;
+        a.mf[3 * p + ax] = mf;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void noslip_of(const PostPassArgs<T> &c, int p) {
+    const PartArgs<T> &a = c.pa;
+    const int lane = threadIdx.x & 63;
+    const int n[3] = {a.G.nx, a.G.ny, a.G.nz};
+    const WaveStencil s = load_stencil(a.bc, a.bf, a.wc, a.wf, p);
+    const T *drho = a.f[0];
+    int bcv[3], bfv[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        bcv[ax] = st_bc(s, ax);
+        bfv[ax] = st_bf(s, ax);
+    }
+    size_t gi[2];
+    double add[2];
+    int cmp[2];
+    bool ok[2];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const int item = lane + 64 * it;
+        ok[it] = item < 81;
+        const int itm = ok[it] ? item : 0;
+        const int fa = itm / 27, pt = itm - 27 * fa;
+        const int d[3] = {pt % 3, (pt / 3) % 3, pt / 9};
+        int pos[3];
+        double po = 1.0;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            pos[ax] = wrap((ax == fa ? bfv[ax] : bcv[ax]) + d[ax], n[ax]);
+            const double wv = st_wc(s, ax, d[ax]);
+            if (ax != fa) po *= wv;
+        }
+        const double wf = st_wf(s, fa, d[fa]);
+        int nb[3] = {pos[0], pos[1], pos[2]};
+        nb[fa] = nb[fa] + 1 == n[fa] ? 0 : nb[fa] + 1;
+        const size_t g = ((size_t)pos[2] * a.G.ny + pos[1]) * a.G.nx + pos[0];
+        const size_t j = ((size_t)nb[2] * a.G.ny + nb[1]) * a.G.nx + nb[0];
+        double v = 0.0;
+        if (ok[it]) {
+            const double rf = a.G.rho0 + 0.5 * ((double)drho[g] + (double)drho[j]);
+            v = rf * a.du[3 * p + fa] * (po * wf) * c.inv_h3;
+        }
+        gi[it] = g;
+        add[it] = v;
+        cmp[it] = fa;
+    }
+    T old[2];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) old[it] = ok[it] ? c.g[cmp[it]][gi[it]] : (T)0;
+#pragma unroll
+    for (int it = 0; it < 2; ++it)
+        if (ok[it]) c.g[cmp[it]][gi[it]] = (T)((double)old[it] + add[it]);
+}
+
+template <typename T>
+__device__ __forceinline__ void final_of(const PartArgs<T> &a, int p) {
+    const int lane = threadIdx.x & 63;
+    const double qh[3] = {a.qh[3 * p], a.qh[3 * p + 1], a.qh[3 * p + 2]};
+    double jv[3];
+    wave_face_sums<T>(a.G, a.f, qh, jv, nullptr);
+    if (lane < 3) {
+        const int ax = lane;
+        const double q = a.q[3 * p + ax];
+        const double qn = q + 0.5 * a.dt * (jv[ax] + a.jv_old[3 * p + ax]);
+        if (isfinite(qn))
+            a.q[3 * p + ax] = wrap_pos(qn, a.L[ax]);
+        else
+            a.flag[2] = 1;
+        const double un = a.Vt[3 * p + ax];
+        const double F = a.F[3 * p + ax];
+        const double lam = a.me[p] * (un - a.u[3 * p + ax]) / a.dt - F;
+        a.sum_f[3 * p + ax] += -(F - a.fext[3 * p + ax]);
+        a.sum_l[3 * p + ax] += lam;
+        a.u[3 * p + ax] = un;
+        a.jv_new[3 * p + ax] = jv[ax];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cl_post(const PostPassArgs<T> c) {
+    const PartArgs<T> &a = c.pa;
+    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (p >= a.np || c.root[p] != p) return;
+    const int k = c.cnt[p], o = c.off[p];
+    int m = p;
+    for (int i = 0; i < k; ++i) {
+        if (i) m = cluster_next(c.list, o, k, m);
+        impulse_of(a, m);
+    }
+    member_fence();
+    m = p;
+    for (int i = 0; i < k; ++i) {
+        if (i) {
+            m = cluster_next(c.list, o, k, m);
+        }
+        noslip_of(c, m);
+        member_fence();
+    }
+    m = p;
+    for (int i = 0; i < k; ++i) {
+        if (i) m = cluster_next(c.list, o, k, m);
+        final_of(a, m);
     }
 }
 
@@ -2345,6 +2854,40 @@ void launch_binning(ic_ctx *c, int np, const double *qh, hipStream_t s) {
     hipLaunchKernelGGL(k_bin_sort, dim3(b.nblk), dim3(64), 0, s, b);
 }
 
+ClusterArgs cluster_args(ic_ctx *c, int np) {
+    const Workspace &w = c->ws;
+    ClusterArgs a{};
+    a.np = np;
+    a.parent = w.cl_parent;
+    a.root = w.cl_root;
+    a.cnt = w.cl_cnt;
+    a.off = w.cl_off;
+    a.cursor = w.cl_cursor;
+    a.list = w.cl_list;
+    return a;
+}
+
+// Clusters of the particles at q^{n+1/2} (after k_pre wrote the kernel
+// data): one workgroup for small sets, else tile binning, unions per tile
+// list, then count, scan and fill.
+void launch_clusters(ic_ctx *c, int np, hipStream_t s) {
+    const ClusterArgs ca = cluster_args(c, np);
+    if (np <= CL_SMALL_CAP) {
+        hipLaunchKernelGGL(k_cl_small, dim3(1), dim3(1024), 0, s, ca, c->ws.pk.bc, c->p.nx,
+                           c->p.ny, c->p.nz);
+        return;
+    }
+    const BinArgs b = bin_args(c, np, c->ws.qh);
+    hipLaunchKernelGGL(k_cl_init, dim3(thread_blocks(np)), dim3(256), 0, s, ca);
+    hipLaunchKernelGGL(k_bin_count, dim3(thread_blocks(np)), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, b);
+    hipLaunchKernelGGL(k_bin_fill, dim3(thread_blocks(np)), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_bin_union, dim3(b.nblk), dim3(64), 0, s, b, ca.parent);
+    hipLaunchKernelGGL(k_cl_count, dim3(thread_blocks(np)), dim3(256), 0, s, ca);
+    hipLaunchKernelGGL(k_cl_scan, dim3(1), dim3(1024), 0, s, ca);
+    hipLaunchKernelGGL(k_cl_fill, dim3(thread_blocks(np)), dim3(256), 0, s, ca);
+}
+
 template <typename T>
 SparseArgs<T> sparse_args(ic_ctx *c) {
     const ic_params &p = c->p;
@@ -2406,7 +2949,7 @@ hipError_t step_impl(ic_ctx *c, bool overlap, bool first, bool last) {
     }
     if (np > 0) {
         hipLaunchKernelGGL(k_pre<T>, dim3(wave_blocks(np)), dim3(256), 0, ps, pa);
-        launch_binning(c, np, w.qh, ps);
+        launch_clusters(c, np, ps);
         if (side_part) chk(hipEventRecord(c->ev_part, c->side));
     }
 
@@ -2460,20 +3003,12 @@ hipError_t step_impl(ic_ctx *c, bool overlap, bool first, bool last) {
     void *const B[4] = {w.B[0], w.B[1], w.B[2], w.B[3]};
     void *const *src[3] = {U, A, B};
     void *const *dst[3] = {A, B, U};
-    // Omega of stage st lives in omega[st & 1] (k_pre writes stage 0's).
-    // Unless the next step's noise runs beside this step, the sparse pass
-    // after stage st also computes stage st + 1's into the other half (two
-    // launches fewer per step); beside that noise, separate k_omega launches
-    // measured faster, as the noise kernel then overlaps them rather than
-    // the stage kernels.
+    // Omega of stage st lives in omega[st & 1]: k_pre writes stage 0's, and
+    // the particle pass after stage st computes stage st + 1's from the
+    // density stage st wrote.
     const size_t ostride = (size_t)(p.max_particles > 0 ? p.max_particles : 0);
-    const bool fuse_omega = !ahead;
+    const ClusterArgs ca = cluster_args(c, np);
     for (int st = 0; st < 3; ++st) {
-        if (np > 0 && st > 0 && !fuse_omega) {
-            pa.omega = w.omega + (st & 1) * ostride;
-            hipLaunchKernelGGL(k_omega<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa,
-                               (const T *)src[st][0]);
-        }
         for (int i = 0; i < 4; ++i) {
             a.in[i] = (const T *)src[st][i];
             a.un[i] = (const T *)U[i];
@@ -2507,29 +3042,32 @@ hipError_t step_impl(ic_ctx *c, bool overlap, bool first, bool last) {
         }
         if (np > 0) {
             if (st == 0 && side_part) chk(hipStreamWaitEvent(s, c->ev_part, 0));
-            SparseArgs<T> sa = sparse_args<T>(c);
-            sa.b = rb[st];
-            sa.val = w.F;
-            sa.omega = w.omega + (st & 1) * ostride;
-            if (fuse_omega && st < 2) {
-                sa.omega_next = w.omega + ((st + 1) & 1) * ostride;
-                sa.drho_next = (const T *)dst[st][0];
-                sa.eps = w.eps;
-                sa.V = 8.0 * p.h * p.h * p.h;
-            }
-            for (int i = 0; i < 3; ++i) sa.fields[i] = (T *)dst[st][1 + i];
-            hipLaunchKernelGGL((k_sparse<T, SP_STAGE>), grid, dim3(SP_THREADS), 0, s, sa);
+            StagePassArgs<T> sp{};
+            sp.nx = p.nx; sp.ny = p.ny; sp.nz = p.nz; sp.np = np;
+            sp.inv_h3 = 1.0 / (p.h * p.h * p.h);
+            sp.b = rb[st];
+            sp.dt_h = p.dt / p.h;
+            sp.dt = p.dt;
+            sp.V = 8.0 * p.h * p.h * p.h;
+            sp.root = ca.root; sp.cnt = ca.cnt; sp.off = ca.off; sp.list = ca.list;
+            sp.bc = w.pk.bc; sp.bf = w.pk.bf; sp.wc = w.pk.wc; sp.wf = w.pk.wf;
+            sp.F = w.F;
+            sp.omega = w.omega + (st & 1) * ostride;
+            sp.eps = w.eps;
+            sp.omega_next = st < 2 ? w.omega + ((st + 1) & 1) * ostride : nullptr;
+            sp.drho_next = (const T *)dst[st][0];
+            for (int i = 0; i < 3; ++i) sp.g[i] = (T *)dst[st][1 + i];
+            hipLaunchKernelGGL(k_cl_stage<T>, dim3(wave_blocks(np)), dim3(256), 0, s, sp);
         }
     }
 
     if (np > 0) {
-        hipLaunchKernelGGL(k_post<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa);
-        SparseArgs<T> sa = sparse_args<T>(c);
-        sa.val = w.du;
-        for (int i = 0; i < 3; ++i) sa.fields[i] = (T *)U[1 + i];
-        sa.drho = (const T *)U[0];
-        hipLaunchKernelGGL((k_sparse<T, SP_NOSLIP>), grid, dim3(SP_THREADS), 0, s, sa);
-        hipLaunchKernelGGL(k_final<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa);
+        PostPassArgs<T> pp{};
+        pp.pa = pa;
+        pp.root = ca.root; pp.cnt = ca.cnt; pp.off = ca.off; pp.list = ca.list;
+        for (int i = 0; i < 3; ++i) pp.g[i] = (T *)U[1 + i];
+        pp.inv_h3 = 1.0 / (p.h * p.h * p.h);
+        hipLaunchKernelGGL(k_cl_post<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pp);
     }
     if (ahead) chk(hipStreamWaitEvent(s, c->ev_noise, 0));
     chk(hipGetLastError());

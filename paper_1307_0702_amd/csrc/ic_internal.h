@@ -63,11 +63,17 @@ struct Workspace {
     PartKernel pk;
     // binning of particles into stage blocks
     int32_t *blk_count, *blk_off, *blk_cursor, *blk_list, *blk_key;
+    // clusters of particles with intersecting influence boxes ([N] each,
+    // cl_off [N + 1]): union-find forest, roots, member counts and offsets
+    // per root, fill cursors, members grouped by root
+    int32_t *cl_parent, *cl_root, *cl_cnt, *cl_off, *cl_cursor, *cl_list;
     // accumulators
     double *sum_f, *sum_l;
     // forcing profiles [IC_MAX_MODES][pmax]
     double *prof;
-    // reductions and flags
+    // reductions and flags: flag[0] m_e + m_f <= 0 in a step, flag[1] a
+    // non-finite position given to a reversed step, flag[2] a non-finite
+    // particle position, velocity or impulse in a step
     double *red;
     int32_t *flag;
     StepState *st;

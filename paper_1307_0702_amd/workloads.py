@@ -252,6 +252,50 @@ def standing_wave_32(x=4.0):
     return Workload("standing-wave-32", fl, p, [mode], drho, g, nT)
 
 
+# Sec. VI, Table I: the paper's own force runs.  Fig. "force" (dipolar):
+# zeta = 1, omega = 0.0784137, m_e = 8000, c_p = 4, measured drho 0.00240249;
+# Fig. "force3" (monopolar): zeta = 0.5, omega = 0.0784134, m_e = 0, c_p = 8,
+# measured drho 0.00339202.  Shared: h = 10, 32^3 cells, rho0 = 1, eta = 0.5,
+# c_f = 4, Kronecker-plane pressure drive of amplitude 0.005.
+TABLE1 = {
+    "force": dict(zeta=1.0, omega=0.0784137, me=8000.0, cp=4.0, drho=0.00240249),
+    "force3": dict(zeta=0.5, omega=0.0784134, me=0.0, cp=8.0, drho=0.00339202),
+}
+
+
+def table1(fig, particles=True, steps_per_period=320, dp=0.005):
+    """The Table I configuration of figure `fig` ("force" or "force3") in the
+    paper's units, with the paper-literal plane drive p_ext = dp sin(omega t)
+    on the cells of the plane x = 0 (Sec. VI, Eq. pext; the wave runs along x
+    here).  No time step is printed: dt = 2 pi / (omega steps_per_period), so
+    a drive period is a whole number of steps (c_f dt / h = 0.100).  The
+    fluid starts on the resonant mode's linear steady state,
+    drho = D cos(k x) cos(omega t) with D = 2 (h/L) dp / (nu_L omega) (the
+    k = 2 pi / L part of the plane drive is 2 (h/L) dp cos(k x)); the other
+    modes the plane excites start at rest.  With particles: the symmetric
+    pair of Sec. VI at (3L/8, L/2, L/2) and (-3L/8, 0, 0) from the driven
+    plane, m_e and c_p of the figure, on soft tethers (reading R9)."""
+    t = TABLE1[fig]
+    fl = Fluid(32, 32, 32, h=10.0, rho0=1.0, cf=4.0, eta=0.5, zeta=t["zeta"], kT=0.0,
+               dt=2.0 * math.pi / (t["omega"] * steps_per_period), seed=1)
+    L = fl.nx * fl.h
+    mode = Mode(axis=0, shape="plane", m=1, x0=0.0, amp=dp, omega=t["omega"])
+    nu_l = (4.0 * fl.eta / 3.0 + fl.zeta) / fl.rho0
+    D = 2.0 * (fl.h / L) * dp / (nu_l * t["omega"])
+    drho, g = standing_wave_fields(fl, D, omega=t["omega"])
+    V = 8.0 * fl.h ** 3
+    if particles:
+        qeq = np.array([[3 * L / 8, L / 2, L / 2], [L - 3 * L / 8, 0.0, 0.0]])
+        mp = t["me"] + fl.rho0 * V
+        p = Particles(q=qeq.copy(), me=np.full(2, t["me"]),
+                      kappa_ratio=np.full(2, (fl.cf / t["cp"]) ** 2),
+                      ks=np.full(2, soft_tether(fl, t["omega"], mp)), qeq=qeq)
+    else:
+        p = Particles(q=np.zeros((0, 3)), me=np.zeros(0), kappa_ratio=np.zeros(0),
+                      ks=np.zeros(0), qeq=np.zeros((0, 3)))
+    return Workload("table1-" + fig, fl, p, [mode], drho, g, steps_per_period)
+
+
 def thermal_128(n=1000, seed=2):
     fl = Fluid(128, 128, 128, kT=1e-3, seed=seed)
     mode, nT = modal_drive(fl, 1e-2)

@@ -127,3 +127,48 @@ def test_graph_and_tile_errors():
     ic.ic_profile(sim.ctx, 0)
     g = ic.ic_graph_create([sim.ctx], 2)
     ic.ic_graph_destroy(g)
+
+
+def test_graph_member_with_replica_id_matches_oracle():
+    # The replica id is the fourth Philox counter word (reading R14): a member
+    # with replica id 3, advanced inside an ensemble graph, must draw the
+    # oracle's noise for replica 3 (FP64, 1e-12), and differ from replica 0.
+    from oracle import ic_oracle as O
+    from paper_1307_0702_amd.ensemble import Ensemble
+    from tests.oracle_state import make_state, modes_of
+    ws = []
+    for r, (nx, ny, nz, npart) in zip((0, 3, 5), [(24, 20, 18, 4), (28, 18, 20, 5), (20, 20, 20, 2)]):
+        w = W.small_random(nx=nx, ny=ny, nz=nz, npart=npart, seed=70, kT=1e-3, min_sep=3.5)
+        w.fluid.replica = r
+        ws.append(w)
+    print("ensemble replica ids 0, 3, 5 against the oracle, fp64", flush=True)
+    ens = Ensemble(ws, prec="fp64", tune=False)
+    ens.capture(2)
+    ens.run()
+    ens.run()
+    w = ws[1]
+    st = make_state(w)
+    prm = w.fluid.as_dict()
+    assert prm["replica"] == 3
+    for _ in range(4):
+        st, _ = O.ic_step(st, prm, modes_of(w))
+    got = _snapshot(ens.sims[1])
+    want = [st["drho"]] + list(st["g"]) + [st["q"], st["u"]]
+    names = ["drho", "gx", "gy", "gz", "q", "u"]
+    L = np.array([w.fluid.nx, w.fluid.ny, w.fluid.nz]) * w.fluid.h
+    for name, a, b in zip(names, got, want):
+        if name == "q":
+            d = np.abs(a - b)
+            err = np.max(np.minimum(d, L - d)) / w.fluid.h
+        else:
+            err = np.max(np.abs(a - b)) / np.max(np.abs(b))
+        print(f"  replica 3 {name}: {err:.2e}", flush=True)
+        assert err <= 1e-12, (name, err)
+    # the same member's oracle run with replica 0 draws other normals
+    st0 = make_state(w)
+    prm0 = dict(prm, replica=0)
+    st0, _ = O.ic_step(st0, prm0, modes_of(w))
+    st3 = make_state(w)
+    st3, _ = O.ic_step(st3, prm, modes_of(w))
+    assert np.max(np.abs(st0["drho"] - st3["drho"])) > 1e-4
+    ens.release()

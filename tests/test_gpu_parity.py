@@ -285,3 +285,40 @@ def test_error_codes_from_device_paths():
     with pytest.raises(ic.ICError) as e:
         sim.set_particles(np.zeros((5, 3)), np.zeros(5), np.zeros(5))
     assert e.value.code == ic.IC_E_CAPACITY
+
+
+def test_non_finite_state_is_reported_and_every_kernel_exits():
+    # A NaN density cell next to a particle makes J v, q^{n+1/2} and the
+    # impulse non-finite.  The step replaces such positions by 0 before any
+    # point index is formed (so every kernel exits normally), keeps the old
+    # position, and the next synchronising call reports IC_E_ARG
+    # ("non-finite state"), not IC_E_MASS.
+    from paper_1307_0702_amd import ic
+    w = W.small_random(nx=20, ny=16, nz=14, npart=3, seed=31, kT=0.0, min_sep=3.5)
+    q0 = np.array(w.particles.q[0])
+    i, j, k = (np.floor(q0 / w.fluid.h + 0.5).astype(int) % [w.fluid.nx, w.fluid.ny, w.fluid.nz])
+    bad = w.drho.copy()
+    bad[k, j, i] = np.nan
+    sim = _sim(w)
+    sim.set_state(bad, w.g)
+    print("non-finite density next to particle 0, fp64", flush=True)
+    sim.step(2)
+    with pytest.raises(ic.ICError) as e:
+        sim.get_particles()
+    assert e.value.code == ic.IC_E_ARG
+    assert "non-finite" in str(e.value)
+    # the flag was cleared, positions stayed finite and inside the box
+    q, _ = sim.get_particles()
+    L = np.array([w.fluid.nx, w.fluid.ny, w.fluid.nz]) * w.fluid.h
+    assert np.all(np.isfinite(q)) and np.all(q >= 0) and np.all(q < L)
+    # a finite state steps normally again
+    sim.set_state(w.drho, w.g)
+    eps = np.array([ic.ic_eps_from_kappa_ratio(w.fluid.cf, r) for r in w.particles.kappa_ratio])
+    p = w.particles
+    sim.set_particles(p.q, p.me, eps, u=p.u, ks=p.ks, qeq=p.qeq, fext=p.fext)
+    sim.step(1)
+    q, u = sim.get_particles()
+    assert np.all(np.isfinite(q)) and np.all(np.isfinite(u))
+    # J at a non-finite position is NaN, not an out-of-bounds gather
+    out = sim.interpolate(np.array([[np.nan, 1.0, 1.0], [2.0, 3.0, 4.0]]), ic.IC_CELL, sim.U[0])
+    assert np.isnan(out[0]) and np.isfinite(out[1])

@@ -118,9 +118,9 @@ def test_radiation_force_dipolar():
 
 
 def test_radiation_force_monopolar():
-    # c_p = 2 c_f: kappa_p = kappa_f / 4, f1 = 0.75.  The model's monopolar
-    # force falls about 10% below Gor'kov (the paper reports deviations of
-    # that size for the monopolar term).
+    # c_p = 2 c_f: kappa_p = kappa_f / 4, f1 = 0.75, in a box of 32 h.  At
+    # this box size the paper reports monopolar deviations of up to about 10%
+    # from Gor'kov (Sec. VI A); the model's force is about 10% low.
     f, gork, _, _ = radiation_force(me=0.0, kappa_ratio=0.25)
     assert np.all(np.sign(f[:, 0]) == np.sign(gork))
     r = f[:, 0] / gork
@@ -136,42 +136,62 @@ def test_radiation_force_soft_monopolar_particle():
     assert np.all(np.abs(r - 1) < 0.04), r
 
 
+OPEN_MONOPOLAR = ("open discrepancy with Sec. VI A: the paper's monopolar deviation (about 10% "
+                  "at 32 h) tends to zero as the box grows; the model's stiff-particle deficit "
+                  "stays near 10% in larger and wider boxes")
+
+
+@pytest.mark.xfail(strict=True, reason=OPEN_MONOPOLAR)
 def test_radiation_force_lateral_box_size():
     # Wavelength fixed at 32h, box widened to 64h across the wave: periodic
-    # images twice as far.  The stiff-particle ratio does not move toward 1,
-    # so its deficit is not an image effect in this model.
+    # images twice as far.  If the 32 h deficit were an image effect, as the
+    # paper's finite-size argument has it, the ratio would move toward 1.
     f, gork, _, _ = radiation_force(me=0.0, kappa_ratio=0.25, Lt=64, nper=8)
     r = f[:, 0] / gork
     print(f"  32 x 64 x 64 monopolar ratio {r}", flush=True)
-    assert np.all((r > 0.85) & (r < 0.95)), r
+    assert np.all(np.abs(r - 1) < 0.05), r
 
 
-def test_radiation_force_frequency_dependence():
+def test_radiation_force_frequency_dependence_dipolar():
     # Box 64h, second mode (wavelength 32h): twice the frequency of the first
-    # mode in the same box.  The stiff-particle deficit grows with omega (to
-    # 13.6% from 9.3% with the first mode at 64h, measured); the dipolar
-    # ratio stays within a few per cent of 1.
+    # mode in the same box.  The dipolar ratio stays within a few per cent
+    # of 1.
     f, gork, _, _ = radiation_force(me=V, kappa_ratio=1.0, L=64, m=2, nper=8)
     rd = f[:, 0] / gork
+    print(f"  L = 64, m = 2: dipolar ratio {rd}", flush=True)
+    assert np.all(np.abs(rd - 1) < 0.05), rd
+
+
+@pytest.mark.xfail(strict=True, reason=OPEN_MONOPOLAR)
+def test_radiation_force_frequency_dependence_monopolar():
+    # Same box and mode for the stiff particle: the periodic images are twice
+    # as far (in wavelengths) as in the 32 h box, so under the paper's
+    # finite-size argument the deficit would have shrunk.
     f, gork, _, _ = radiation_force(me=0.0, kappa_ratio=0.25, L=64, m=2, nper=8)
     rm = f[:, 0] / gork
-    print(f"  L = 64, m = 2: dipolar ratio {rd}, monopolar ratio {rm}", flush=True)
-    assert np.all(np.abs(rd - 1) < 0.05), rd
-    assert np.all((rm > 0.82) & (rm < 0.90)), rm
+    print(f"  L = 64, m = 2: monopolar ratio {rm}", flush=True)
+    assert np.all(np.abs(rm - 1) < 0.05), rm
 
 
 @pytest.mark.parametrize("L", [48, 64])
-def test_radiation_force_finite_size(L):
-    # Box sizes 48h and 64h (kR_a = 0.16 and 0.12 against 0.24 at 32h): the
-    # ratios to Gor'kov stay where they are at 32h, so neither the dipolar
-    # agreement nor the monopolar deficit is a finite-size effect of the box.
+def test_radiation_force_finite_size_dipolar(L):
+    # Box sizes 48h and 64h (kR_a = 0.16 and 0.12 against 0.24 at 32h).
     f, gork, _, _ = radiation_force(me=V, kappa_ratio=1.0, L=L, nper=8)
     rd = f[:, 0] / gork
+    print(f"  L = {L}: dipolar ratio {rd}", flush=True)
+    assert np.all(np.abs(rd - 1) < 0.05), rd
+
+
+@pytest.mark.xfail(strict=True, reason=OPEN_MONOPOLAR)
+@pytest.mark.parametrize("L,bound", [(48, 0.07), (64, 0.05)])
+def test_radiation_force_finite_size_monopolar(L, bound):
+    # The paper: the about-10% monopolar deviation at 32 h tends to zero as
+    # the box grows (Sec. VI A); at least as 1/L, it would be below 7% at
+    # 48 h and 5% at 64 h.
     f, gork, _, _ = radiation_force(me=0.0, kappa_ratio=0.25, L=L, nper=8)
     rm = f[:, 0] / gork
-    print(f"  L = {L}: dipolar ratio {rd}, monopolar ratio {rm}", flush=True)
-    assert np.all(np.abs(rd - 1) < 0.05), rd
-    assert np.all((rm > 0.85) & (rm < 0.95)), rm
+    print(f"  L = {L}: monopolar ratio {rm}", flush=True)
+    assert np.all(np.abs(rm - 1) < bound), rm
 
 
 def test_radiation_force_negative_contrast():
