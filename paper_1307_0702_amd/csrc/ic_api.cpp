@@ -226,6 +226,7 @@ struct ic_graph {
     hipGraphExec_t exec = nullptr;
     std::vector<ic_ctx *> ctxs;
     int64_t nsteps = 0;
+    ic::Batch *batch = nullptr;   // batched steps' device tables (or none: one chain per context)
 };
 
 
@@ -855,6 +856,13 @@ int ic_graph_create(ic_ctx *const *ctxs, int32_t n, int64_t nsteps, ic_graph **o
     if (!g) return IC_E_ARG;
     g->ctxs.assign(ctxs, ctxs + n);
     g->nsteps = nsteps;
+    if (batch_supported(ctxs, n)) {
+        const hipError_t eb = batch_create(ctxs, n, &g->batch);
+        if (eb != hipSuccess) {
+            delete g;
+            return hip_fail(ctxs[0], eb, "graph: batch tables");
+        }
+    }
     // one branch stream per context, forked from and joined into an origin
     // stream that is captured (default priorities throughout)
     hipStream_t origin = nullptr;
@@ -872,18 +880,24 @@ int ic_graph_create(ic_ctx *const *ctxs, int32_t n, int64_t nsteps, ic_graph **o
         e = hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal);
         capturing = e == hipSuccess;
     }
-    if (e == hipSuccess) e = hipEventRecord(fork, origin);
-    for (int32_t i = 0; i < n && e == hipSuccess; ++i) {
-        ic_ctx *c = ctxs[i];
-        e = hipStreamWaitEvent(br[i], fork, 0);
-        const hipStream_t own = c->stream;
-        c->stream = br[i];
-        // single-stream steps: a second stream forked from the branch stream
-        // would nest one capture join inside another
-        for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) e = launch_step(c, false, true, true);
-        c->stream = own;
-        if (e == hipSuccess) e = hipEventRecord(join[i], br[i]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(origin, join[i], 0);
+    if (e == hipSuccess && g->batch) {
+        // batched: each kernel of a step once for every context
+        for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) e = batch_step(g->batch, origin);
+    } else if (e == hipSuccess) {
+        e = hipEventRecord(fork, origin);
+        for (int32_t i = 0; i < n && e == hipSuccess; ++i) {
+            ic_ctx *c = ctxs[i];
+            e = hipStreamWaitEvent(br[i], fork, 0);
+            const hipStream_t own = c->stream;
+            c->stream = br[i];
+            // single-stream steps: a second stream forked from the branch
+            // stream would nest one capture join inside another
+            for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s)
+                e = launch_step(c, false, true, true);
+            c->stream = own;
+            if (e == hipSuccess) e = hipEventRecord(join[i], br[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(origin, join[i], 0);
+        }
     }
     if (capturing) {
         const hipError_t e2 = hipStreamEndCapture(origin, &g->graph);
@@ -899,6 +913,7 @@ int ic_graph_create(ic_ctx *const *ctxs, int32_t n, int64_t nsteps, ic_graph **o
     if (e != hipSuccess) {
         if (g->exec) (void)hipGraphExecDestroy(g->exec);
         if (g->graph) (void)hipGraphDestroy(g->graph);
+        batch_destroy(g->batch);
         delete g;
         return hip_fail(ctxs[0], e, "graph capture");
     }
@@ -921,6 +936,7 @@ int ic_graph_destroy(ic_graph *g) {
     if (!g) return IC_E_ARG;
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
+    batch_destroy(g->batch);
     delete g;
     return IC_OK;
 }

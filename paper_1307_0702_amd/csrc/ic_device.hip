@@ -20,13 +20,34 @@
 // results are bitwise reproducible.
 #include <math.h>
 
+#include <algorithm>
+#include <cstring>
 #include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "ic_internal.h"
 
+// Multiply-adds are fused only where one source expression holds both (not
+// across statements), so the code a kernel body compiles to does not depend
+// on the kernel it is inlined into: the batched ensemble kernels then give
+// the single-context kernels' results bit for bit.
+#pragma clang fp contract(on)
+
+// Argument tables of the batched ensemble kernels live in global memory that
+// no kernel writes: declared constant (address space 4), their loads are
+// scalar and may be repeated at any point, as kernel arguments are.
+#define IC_CONST __attribute__((address_space(4)))
+
 namespace ic {
 namespace {
+
+// A table entry viewed through an ordinary reference (the compiler still sees
+// where it points).
+template <typename X>
+__device__ __forceinline__ const X &from_const(const IC_CONST X &r) {
+    return *(const X *)&r;
+}
 
 // ---------------------------------------------------------------------------
 // 3-point function of Roma and Peskin (App. A, "Spatial discretization").
@@ -240,6 +261,7 @@ struct StageArgs {
     // NOISE only; step n reads set n & 1 (StepState.cur)
     const T *noise[2][3];
     const StepState *st;
+    int full;         // every tile whole (nx, ny multiples of TX, TY)
     // imposed pressure: sum_m amp[m] * prof[m][coord(maxis[m])], amp at this
     // stage's time (StepState, device)
     int nmodes;
@@ -319,25 +341,29 @@ __device__ __forceinline__ T ext_pressure_z(const StageArgs<T> &a, int z) {
 // the fluxes the tile's own faces need there) and wave 4 the rest of the
 // density ring.  Register sets for planes k+1 and k+2 alternate, so every
 // load is issued one iteration before its use.
+// Workgroups go to the 8 XCDs round-robin; tile index of workgroup b among
+// nblk that gives each XCD a contiguous run of tiles (x fastest), so tiles
+// sharing halo lines share one L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblk) {
+    const int per = nblk / 8, rem = nblk % 8, xcd = b % 8, idx = b / 8;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+constexpr int STAGE_LDS = 14 * PS;   // elements of LDS a stage tile uses
+
+// One RK stage over tile t of the context's grid; lds holds STAGE_LDS
+// elements.
 template <typename T, int STAGE, bool NOISE, bool FULL>
-__global__ __launch_bounds__(STAGE_THREADS)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void stage_kernel(const StageArgs<T> a) {
-    __shared__ T s_G[3][PS], s_V[3][PS], s_P[2][PS], s_F[6][PS];
+__device__ __forceinline__ void stage_body(const StageArgs<T> &a, int t, T *lds) {
+    T(*s_G)[PS] = reinterpret_cast<T(*)[PS]>(lds);
+    T(*s_V)[PS] = reinterpret_cast<T(*)[PS]>(lds + 3 * PS);
+    T(*s_P)[PS] = reinterpret_cast<T(*)[PS]>(lds + 6 * PS);
+    T(*s_F)[PS] = reinterpret_cast<T(*)[PS]>(lds + 8 * PS);
 
     const int nx = a.nx, ny = a.ny, nz = a.nz, tz = a.tz;
     const uint32_t pbytes = (uint32_t)nx * (uint32_t)ny * (uint32_t)sizeof(T);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    // Workgroups go to the 8 XCDs round-robin; give each XCD a contiguous run
-    // of tiles (x fastest) so tiles sharing halo lines share one L2.
-    int bx, by, bz;
-    {
-        const int nblk = a.gx * a.gy * a.gz, b = blockIdx.x;
-        const int per = nblk / 8, rem = nblk % 8, xcd = b % 8, idx = b / 8;
-        const int t = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-        bx = t % a.gx;
-        by = (t / a.gx) % a.gy;
-        bz = t / (a.gx * a.gy);
-    }
+    const int bx = t % a.gx, by = (t / a.gx) % a.gy, bz = t / (a.gx * a.gy);
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * tz;   // z0 is even (tz is)
     // FULL: every tile is whole (nx, ny multiples of TX, TY)
     const int W = FULL ? TX : min(TX, nx - x0), Wy = FULL ? TY : min(TY, ny - y0);
@@ -636,6 +662,40 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void stage_kernel(c
     }
 }
 
+#define IC_STAGE_ATTRS                   \
+    __global__ __launch_bounds__(STAGE_THREADS) \
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4)))
+
+template <typename T, int STAGE, bool NOISE, bool FULL>
+IC_STAGE_ATTRS void stage_kernel(const StageArgs<T> a) {
+    __shared__ T s_lds[STAGE_LDS];
+    stage_body<T, STAGE, NOISE, FULL>(a, xcd_tile(blockIdx.x, a.gx * a.gy * a.gz), s_lds);
+}
+
+// One RK stage over the tiles of many contexts at once (ensembles): block b
+// runs tile tile[b] of context member[b] with that context's arguments
+// (args[member]); noise and whole-tile specialisation per context.
+template <typename T, int STAGE>
+IC_STAGE_ATTRS void stage_kernel_batched(const IC_CONST StageArgs<T> *args,
+                                         const IC_CONST int32_t *member,
+                                         const IC_CONST int32_t *tile) {
+    __shared__ T s_lds[STAGE_LDS];
+    const StageArgs<T> &a = from_const(args[member[blockIdx.x]]);
+    const int t = tile[blockIdx.x];
+    if (a.noise[0][0]) {
+        if (a.full)
+            stage_body<T, STAGE, true, true>(a, t, s_lds);
+        else
+            stage_body<T, STAGE, true, false>(a, t, s_lds);
+    } else {
+        if (a.full)
+            stage_body<T, STAGE, false, true>(a, t, s_lds);
+        else
+            stage_body<T, STAGE, false, false>(a, t, s_lds);
+    }
+}
+#undef IC_STAGE_ATTRS
+
 // ---------------------------------------------------------------------------
 // Stochastic increments of one step.  The stochastic flux enters each RK
 // stage linearly and does not depend on the state, so its increment
@@ -668,25 +728,19 @@ constexpr int NOISE_THREADS = NTX * NTY<T>;
 
 __device__ __forceinline__ int nidx(int lx, int ly) { return (ly + 1) * NPX + (lx + 1); }
 
+// Noise of tile t (of a.gx x a.gy x a.gz tiles); s_S holds the current
+// plane's stresses [W_A, W_B][xx, yy, xy, xz, yz].
 template <typename T>
-__global__ __launch_bounds__(NOISE_THREADS<T>) void noise_kernel(const NoiseArgs<T> args) {
+__device__ __forceinline__ void noise_body(const NoiseArgs<T> &args, int t,
+                                           T (*s_S)[5][NPX * (NTY<T> + 2)]) {
     NoiseArgs<T> a = args;
     const uint32_t m = args.step->cur + args.ahead;
     a.nk.step = m;
     T *const *out = (m & 1u) ? args.out[1] : args.out[0];
-    __shared__ T s_S[2][5][NPX * (NTY<T> + 2)];  // [W_A, W_B][xx, yy, xy, xz, yz], current plane
     const int nx = a.nx, ny = a.ny, nz = a.nz, tz = a.tz;
     const int plane = nx * ny;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    int bx, by, bz;
-    {
-        const int nblk = a.gx * a.gy * a.gz, b = blockIdx.x;
-        const int per = nblk / 8, rem = nblk % 8, xcd = b % 8, idx = b / 8;
-        const int t = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
-        bx = t % a.gx;
-        by = (t / a.gx) % a.gy;
-        bz = t / (a.gx * a.gy);
-    }
+    const int bx = t % a.gx, by = (t / a.gx) % a.gy, bz = t / (a.gx * a.gy);
     const int x0 = bx * NTX, y0 = by * NTY<T>, z0 = bz * tz;
     const int W = min(NTX, nx - x0), Wy = min(NTY<T>, ny - y0), z1 = min(z0 + tz, nz);
     const int lx = tid % NTX, ly = tid / NTX;
@@ -780,6 +834,22 @@ __global__ __launch_bounds__(NOISE_THREADS<T>) void noise_kernel(const NoiseArgs
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(NOISE_THREADS<T>) void noise_kernel(const NoiseArgs<T> args) {
+    __shared__ T s_S[2][5][NPX * (NTY<T> + 2)];
+    noise_body<T>(args, xcd_tile(blockIdx.x, args.gx * args.gy * args.gz), s_S);
+}
+
+// Noise of many contexts in one launch: block b draws tile tile[b] of
+// context member[b].
+template <typename T>
+__global__ __launch_bounds__(NOISE_THREADS<T>) void noise_kernel_batched(
+    const IC_CONST NoiseArgs<T> *args, const IC_CONST int32_t *member,
+    const IC_CONST int32_t *tile) {
+    __shared__ T s_S[2][5][NPX * (NTY<T> + 2)];
+    noise_body<T>(from_const(args[member[blockIdx.x]]), tile[blockIdx.x], s_S);
+}
+
 // ---------------------------------------------------------------------------
 // Per-step scalars (StepState).  One wave: every lane reads the step before
 // lane 0 advances it.
@@ -790,7 +860,7 @@ struct DriveArgs {
     double amp[IC_MAX_MODES], omega[IC_MAX_MODES], phase[IC_MAX_MODES];
 };
 
-__global__ __launch_bounds__(64) void k_step_begin(StepState *st, const DriveArgs d) {
+__device__ __forceinline__ void step_begin_body(StepState *st, const DriveArgs &d) {
     const int lane = threadIdx.x;
     const int64_t n = st->step;
     // stage times t^n, t^n + dt, t^n + dt/2 (App. A, stage pressures)
@@ -805,6 +875,16 @@ __global__ __launch_bounds__(64) void k_step_begin(StepState *st, const DriveArg
         st->cur = (uint32_t)(n & 0xFFFFFFFF);
         st->step = n + 1;
     }
+}
+
+__global__ __launch_bounds__(64) void k_step_begin(StepState *st, const DriveArgs d) {
+    step_begin_body(st, d);
+}
+
+// One block per context.
+__global__ __launch_bounds__(64) void k_step_begin_batched(StepState *const IC_CONST *st,
+                                                           const IC_CONST DriveArgs *d) {
+    step_begin_body(st[blockIdx.x], from_const(d[blockIdx.x]));
 }
 
 __global__ void k_set_step(StepState *st, int64_t n) {
@@ -921,9 +1001,7 @@ struct PartArgs {
 
 // Substeps 1-2 and the kernel data at q^{n+1/2} (App. A).
 template <typename T>
-__global__ __launch_bounds__(256) void k_pre(const PartArgs<T> a) {
-    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (p >= a.np) return;
+__device__ __forceinline__ void pre_body(const PartArgs<T> &a, int p) {
     const int lane = threadIdx.x & 63;
     double q[3] = {a.q[3 * p], a.q[3 * p + 1], a.q[3 * p + 2]};
     // A non-finite position or velocity (NaN or inf in the fields) would
@@ -978,6 +1056,28 @@ __global__ __launch_bounds__(256) void k_pre(const PartArgs<T> a) {
         a.F[3 * p + ax] = -a.ks[p] * min_image(qh[ax] - a.qeq[3 * p + ax], a.L[ax]) +
                           a.fext[3 * p + ax];
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pre(const PartArgs<T> a) {
+    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (p >= a.np) return;
+    pre_body(a, p);
+}
+
+// Waves of many contexts in one launch: wave w handles particle
+// local[w] of context member[w] (member < 0: no work).
+struct WaveMap {
+    const IC_CONST int32_t *member, *local;
+    int nwaves;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pre_batched(const IC_CONST PartArgs<T> *args,
+                                                     const WaveMap map) {
+    const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (w >= map.nwaves) return;
+    pre_body(from_const(args[map.member[w]]), map.local[w]);
 }
 
 // Kernel data for standalone spreading at caller positions.
@@ -1722,8 +1822,14 @@ __global__ __launch_bounds__(256) void k_cl_fill(const ClusterArgs a) {
 // in ascending id).  One launch instead of seven on small particle sets.
 constexpr int CL_SMALL_CAP = 512;
 
-__global__ __launch_bounds__(1024) void k_cl_small(const ClusterArgs a, const int32_t *bc, int nx,
-                                                   int ny, int nz) {
+struct ClusterSmallArgs {
+    ClusterArgs ca;
+    const int32_t *bc;
+    int nx, ny, nz;
+};
+
+__device__ __forceinline__ void cl_small_body(const ClusterArgs &a, const int32_t *bc, int nx,
+                                              int ny, int nz) {
     __shared__ int32_t s_par[CL_SMALL_CAP], s_b[CL_SMALL_CAP][3], s_cnt[CL_SMALL_CAP + 1];
     const int tid = threadIdx.x, np = a.np;
     const int nn[3] = {nx, ny, nz};
@@ -1784,6 +1890,16 @@ __global__ __launch_bounds__(1024) void k_cl_small(const ClusterArgs a, const in
         // members in ascending id: one pass in id order
         for (int p = 0; p < np; ++p) a.list[s_cnt[s_par[p]]++] = p;
     }
+}
+
+__global__ __launch_bounds__(1024) void k_cl_small(const ClusterSmallArgs a) {
+    cl_small_body(a.ca, a.bc, a.nx, a.ny, a.nz);
+}
+
+// One workgroup per context.
+__global__ __launch_bounds__(1024) void k_cl_small_batched(const IC_CONST ClusterSmallArgs *a) {
+    const ClusterSmallArgs &c = from_const(a[blockIdx.x]);
+    cl_small_body(c.ca, c.bc, c.nx, c.ny, c.nz);
 }
 
 // Next member above `last` of the cluster list[o, o + k) (its smallest id
@@ -1935,9 +2051,8 @@ __device__ __forceinline__ void stage_terms_of(const StagePassArgs<T> &a, int p)
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_cl_stage(const StagePassArgs<T> a) {
-    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (p >= a.np || a.root[p] != p) return;
+__device__ __forceinline__ void cl_stage_body(const StagePassArgs<T> &a, int p) {
+    if (a.root[p] != p) return;
     const int k = a.cnt[p];
     if (k == 1) {
         stage_terms_of(a, p);
@@ -1952,6 +2067,21 @@ __global__ __launch_bounds__(256) void k_cl_stage(const StagePassArgs<T> a) {
         }
         stage_terms_of(a, m);
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cl_stage(const StagePassArgs<T> a) {
+    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (p >= a.np) return;
+    cl_stage_body(a, p);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cl_stage_batched(const IC_CONST StagePassArgs<T> *args,
+                                                          const WaveMap map) {
+    const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (w >= map.nwaves) return;
+    cl_stage_body(from_const(args[map.member[w]]), map.local[w]);
 }
 
 // Substeps 4-7 for one cluster per wave (App. A): the impulse and particle
@@ -2074,10 +2204,9 @@ __device__ __forceinline__ void final_of(const PartArgs<T> &a, int p) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_cl_post(const PostPassArgs<T> c) {
+__device__ __forceinline__ void cl_post_body(const PostPassArgs<T> &c, int p) {
     const PartArgs<T> &a = c.pa;
-    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (p >= a.np || c.root[p] != p) return;
+    if (c.root[p] != p) return;
     const int k = c.cnt[p], o = c.off[p];
     int m = p;
     for (int i = 0; i < k; ++i) {
@@ -2098,6 +2227,21 @@ __global__ __launch_bounds__(256) void k_cl_post(const PostPassArgs<T> c) {
         if (i) m = cluster_next(c.list, o, k, m);
         final_of(a, m);
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cl_post(const PostPassArgs<T> c) {
+    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (p >= c.pa.np) return;
+    cl_post_body(c, p);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cl_post_batched(const IC_CONST PostPassArgs<T> *args,
+                                                         const WaveMap map) {
+    const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (w >= map.nwaves) return;
+    cl_post_body(from_const(args[map.member[w]]), map.local[w]);
 }
 
 // ---------------------------------------------------------------------------
@@ -2873,8 +3017,8 @@ ClusterArgs cluster_args(ic_ctx *c, int np) {
 void launch_clusters(ic_ctx *c, int np, hipStream_t s) {
     const ClusterArgs ca = cluster_args(c, np);
     if (np <= CL_SMALL_CAP) {
-        hipLaunchKernelGGL(k_cl_small, dim3(1), dim3(1024), 0, s, ca, c->ws.pk.bc, c->p.nx,
-                           c->p.ny, c->p.nz);
+        hipLaunchKernelGGL(k_cl_small, dim3(1), dim3(1024), 0, s,
+                           ClusterSmallArgs{ca, c->ws.pk.bc, c->p.nx, c->p.ny, c->p.nz});
         return;
     }
     const BinArgs b = bin_args(c, np, c->ws.qh);
@@ -2903,56 +3047,63 @@ SparseArgs<T> sparse_args(ic_ctx *c) {
     return sa;
 }
 
-// One step on the context stream.  Beside it, on the side stream: the
-// particle prologue (half-step positions, kernel weights, stage-1 Omega,
-// binning), which only reads U^n and is joined before the first particle
-// stage term, and (FP32) the noise of the next step, which depends only on
-// the key and the step number, joined at the end of the step: the fluid
-// stages are memory-bound and the noise kernel ALU-bound.
+// Arguments of one context's step kernels (shared by the eager step and the
+// batched ensemble step, so both run the same arithmetic).
+DriveArgs drive_args(const ic_ctx *c) {
+    DriveArgs d{};
+    d.nmodes = c->forcing.nmodes;
+    d.dt = c->p.dt;
+    for (int m = 0; m < d.nmodes; ++m) {
+        d.amp[m] = c->forcing.modes[m].amp;
+        d.omega[m] = c->forcing.modes[m].omega;
+        d.phase[m] = c->forcing.modes[m].phase;
+    }
+    return d;
+}
+
 template <typename T>
-hipError_t step_impl(ic_ctx *c, bool overlap, bool first, bool last) {
+NoiseArgs<T> noise_args(const ic_ctx *c) {
     const ic_params &p = c->p;
-    hipStream_t s = c->stream;
     const Workspace &w = c->ws;
-    void *U[4] = {c->f[0], c->f[1], c->f[2], c->f[3]};
-    const dim3 grid(c->nblk[0], c->nblk[1], c->nblk[2]);
-    const unsigned nblk_all = (unsigned)(c->nblk[0] * c->nblk[1] * c->nblk[2]);
-    const int np = c->np;
-    const bool noise = p.kT > 0.0;
-    // Next-step noise beside the stages in FP32 only: the FP64 noise kernel
-    // is FP64-ALU-bound for about 1.5 stage sweeps and, run concurrently,
-    // slowed the stage kernels by more than it hid (measured at 256^3).
-    if (!overlap || sizeof(T) == 8) first = last = true;
-    const bool ahead = noise && !last;
-    const bool side_part = overlap && np > 0;
-    const hipStream_t ps = side_part ? c->side : s;   // stream of the particle prologue
-    PartArgs<T> pa = part_args<T>(c, U);
-    hipError_t err = hipSuccess;
-    auto chk = [&](hipError_t e) {
-        if (err == hipSuccess) err = e;
-    };
+    NoiseArgs<T> na{};
+    for (int k = 0; k < 2; ++k)
+        for (int i = 0; i < 9; ++i) na.out[k][i] = (T *)w.N[k][i];
+    na.nx = p.nx; na.ny = p.ny; na.nz = p.nz; na.tz = c->tz;
+    na.gx = (p.nx + NTX - 1) / NTX; na.gy = (p.ny + NTY<T> - 1) / NTY<T>; na.gz = c->nblk[2];
+    const double amp = 1.0 / sqrt(p.h * p.h * p.h * p.dt);
+    const double an = sqrt(2.0 * p.eta * p.kT);
+    const double bt = sqrt(p.zeta * p.kT / 3.0) - an / 3.0;
+    na.dt_h = (T)(p.dt / p.h);
+    na.sd = (T)(amp * an * sqrt(2.0));
+    na.st = (T)(amp * bt * sqrt(2.0));
+    na.so = (T)(amp * an);
+    na.s3 = (T)sqrt(3.0);
+    na.nk = NoiseKey{(uint32_t)(p.seed & 0xFFFFFFFFu), (uint32_t)(p.seed >> 32), 0u, p.replica};
+    na.step = w.st;
+    na.ahead = 0;
+    return na;
+}
 
-    {
-        DriveArgs d{};
-        d.nmodes = c->forcing.nmodes;
-        d.dt = p.dt;
-        for (int m = 0; m < d.nmodes; ++m) {
-            d.amp[m] = c->forcing.modes[m].amp;
-            d.omega[m] = c->forcing.modes[m].omega;
-            d.phase[m] = c->forcing.modes[m].phase;
-        }
-        hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(64), 0, s, w.st, d);
-    }
-    if (side_part || ahead) {
-        chk(hipEventRecord(c->ev_fork, s));
-        chk(hipStreamWaitEvent(c->side, c->ev_fork, 0));
-    }
-    if (np > 0) {
-        hipLaunchKernelGGL(k_pre<T>, dim3(wave_blocks(np)), dim3(256), 0, ps, pa);
-        launch_clusters(c, np, ps);
-        if (side_part) chk(hipEventRecord(c->ev_part, c->side));
-    }
+constexpr double RK_A[3] = {0.0, 0.75, 1.0 / 3.0}, RK_B[3] = {1.0, 0.25, 2.0 / 3.0};
 
+// Stage st reads src and writes dst: U -> A -> B -> U.
+struct StageBufs {
+    void *src[4], *dst[4];
+};
+inline StageBufs stage_buffers(const ic_ctx *c, int st) {
+    StageBufs b;
+    for (int i = 0; i < 4; ++i) {
+        void *const chain[4] = {c->f[i], c->ws.A[i], c->ws.B[i], c->f[i]};
+        b.src[i] = chain[st];
+        b.dst[i] = chain[st + 1];
+    }
+    return b;
+}
+
+template <typename T>
+StageArgs<T> stage_args(const ic_ctx *c, int st) {
+    const ic_params &p = c->p;
+    const Workspace &w = c->ws;
     StageArgs<T> a{};
     a.nx = p.nx; a.ny = p.ny; a.nz = p.nz; a.tz = c->tz;
     a.gx = c->nblk[0]; a.gy = c->nblk[1]; a.gz = c->nblk[2];
@@ -2965,23 +3116,105 @@ hipError_t step_impl(ic_ctx *c, bool overlap, bool first, bool last) {
     a.dt = (T)p.dt;
     a.fbytes = (uint32_t)((size_t)p.nx * p.ny * p.nz * sizeof(T));
     a.st = w.st;
-    const bool full = p.nx % TX == 0 && p.ny % TY == 0;
+    a.full = p.nx % TX == 0 && p.ny % TY == 0;
+    a.nmodes = c->forcing.nmodes;
+    a.prof = w.prof;
+    a.pstride = c->prof_stride;
+    for (int m = 0; m < a.nmodes; ++m) a.maxis[m] = c->forcing.modes[m].axis;
+    const StageBufs sb = stage_buffers(c, st);
+    for (int i = 0; i < 4; ++i) {
+        a.in[i] = (const T *)sb.src[i];
+        a.un[i] = (const T *)c->f[i];
+        a.out[i] = (T *)sb.dst[i];
+    }
+    a.ra = (T)RK_A[st];
+    a.rb = (T)RK_B[st];
+    const bool noise = p.kT > 0.0;
+    for (int k = 0; k < 2; ++k)
+        for (int i = 0; i < 3; ++i) a.noise[k][i] = noise ? (const T *)w.N[k][3 * st + i] : nullptr;
+    a.amp = w.st->amp[st];
+    return a;
+}
+
+// Omega of stage st lives in omega[st & 1]: k_pre writes stage 0's, and the
+// particle pass after stage st computes stage st + 1's from the density
+// stage st wrote.
+template <typename T>
+StagePassArgs<T> stage_pass_args(ic_ctx *c, int st) {
+    const ic_params &p = c->p;
+    const Workspace &w = c->ws;
+    const size_t ostride = (size_t)(p.max_particles > 0 ? p.max_particles : 0);
+    const ClusterArgs ca = cluster_args(c, c->np);
+    const StageBufs sb = stage_buffers(c, st);
+    StagePassArgs<T> sp{};
+    sp.nx = p.nx; sp.ny = p.ny; sp.nz = p.nz; sp.np = c->np;
+    sp.inv_h3 = 1.0 / (p.h * p.h * p.h);
+    sp.b = RK_B[st];
+    sp.dt_h = p.dt / p.h;
+    sp.dt = p.dt;
+    sp.V = 8.0 * p.h * p.h * p.h;
+    sp.root = ca.root; sp.cnt = ca.cnt; sp.off = ca.off; sp.list = ca.list;
+    sp.bc = w.pk.bc; sp.bf = w.pk.bf; sp.wc = w.pk.wc; sp.wf = w.pk.wf;
+    sp.F = w.F;
+    sp.omega = w.omega + (st & 1) * ostride;
+    sp.eps = w.eps;
+    sp.omega_next = st < 2 ? w.omega + ((st + 1) & 1) * ostride : nullptr;
+    sp.drho_next = (const T *)sb.dst[0];
+    for (int i = 0; i < 3; ++i) sp.g[i] = (T *)sb.dst[1 + i];
+    return sp;
+}
+
+template <typename T>
+PostPassArgs<T> post_args(ic_ctx *c) {
+    void *U[4] = {c->f[0], c->f[1], c->f[2], c->f[3]};
+    const ClusterArgs ca = cluster_args(c, c->np);
+    PostPassArgs<T> pp{};
+    pp.pa = part_args<T>(c, U);
+    pp.root = ca.root; pp.cnt = ca.cnt; pp.off = ca.off; pp.list = ca.list;
+    for (int i = 0; i < 3; ++i) pp.g[i] = (T *)c->f[1 + i];
+    pp.inv_h3 = 1.0 / (c->p.h * c->p.h * c->p.h);
+    return pp;
+}
+
+// One step on the context stream.  Beside it, on the side stream: the
+// particle prologue (half-step positions, kernel weights, stage-1 Omega,
+// clusters), which only reads U^n and is joined before the first particle
+// stage term, and (FP32) the noise of the next step, which depends only on
+// the key and the step number, joined at the end of the step: the fluid
+// stages are memory-bound and the noise kernel ALU-bound.
+template <typename T>
+hipError_t step_impl(ic_ctx *c, bool overlap, bool first, bool last) {
+    const ic_params &p = c->p;
+    hipStream_t s = c->stream;
+    const Workspace &w = c->ws;
+    void *U[4] = {c->f[0], c->f[1], c->f[2], c->f[3]};
+    const unsigned nblk_all = (unsigned)(c->nblk[0] * c->nblk[1] * c->nblk[2]);
+    const int np = c->np;
+    const bool noise = p.kT > 0.0;
+    // Next-step noise beside the stages in FP32 only: the FP64 noise kernel
+    // is FP64-ALU-bound for about 1.5 stage sweeps and, run concurrently,
+    // slowed the stage kernels by more than it hid (measured at 256^3).
+    if (!overlap || sizeof(T) == 8) first = last = true;
+    const bool ahead = noise && !last;
+    const bool side_part = overlap && np > 0;
+    const hipStream_t ps = side_part ? c->side : s;   // stream of the particle prologue
+    hipError_t err = hipSuccess;
+    auto chk = [&](hipError_t e) {
+        if (err == hipSuccess) err = e;
+    };
+
+    hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(64), 0, s, w.st, drive_args(c));
+    if (side_part || ahead) {
+        chk(hipEventRecord(c->ev_fork, s));
+        chk(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+    }
+    if (np > 0) {
+        hipLaunchKernelGGL(k_pre<T>, dim3(wave_blocks(np)), dim3(256), 0, ps, part_args<T>(c, U));
+        launch_clusters(c, np, ps);
+        if (side_part) chk(hipEventRecord(c->ev_part, c->side));
+    }
     if (noise) {
-        NoiseArgs<T> na{};
-        for (int k = 0; k < 2; ++k)
-            for (int i = 0; i < 9; ++i) na.out[k][i] = (T *)w.N[k][i];
-        na.nx = p.nx; na.ny = p.ny; na.nz = p.nz; na.tz = c->tz;
-        na.gx = (p.nx + NTX - 1) / NTX; na.gy = (p.ny + NTY<T> - 1) / NTY<T>; na.gz = c->nblk[2];
-        const double amp = 1.0 / sqrt(p.h * p.h * p.h * p.dt);
-        const double an = sqrt(2.0 * p.eta * p.kT);
-        const double bt = sqrt(p.zeta * p.kT / 3.0) - an / 3.0;
-        na.dt_h = (T)(p.dt / p.h);
-        na.sd = (T)(amp * an * sqrt(2.0));
-        na.st = (T)(amp * bt * sqrt(2.0));
-        na.so = (T)(amp * an);
-        na.s3 = (T)sqrt(3.0);
-        na.nk = NoiseKey{(uint32_t)(p.seed & 0xFFFFFFFFu), (uint32_t)(p.seed >> 32), 0u, p.replica};
-        na.step = w.st;
+        NoiseArgs<T> na = noise_args<T>(c);
         const dim3 ng(na.gx * na.gy * na.gz), nt(NOISE_THREADS<T>);
         if (ahead) {
             na.ahead = 1;
@@ -2993,32 +3226,9 @@ hipError_t step_impl(ic_ctx *c, bool overlap, bool first, bool last) {
             hipLaunchKernelGGL(noise_kernel<T>, ng, nt, 0, s, na);
         }
     }
-    a.nmodes = c->forcing.nmodes;
-    a.prof = w.prof;
-    a.pstride = c->prof_stride;
-    for (int m = 0; m < a.nmodes; ++m) a.maxis[m] = c->forcing.modes[m].axis;
-
-    const double ra[3] = {0.0, 0.75, 1.0 / 3.0}, rb[3] = {1.0, 0.25, 2.0 / 3.0};
-    void *const A[4] = {w.A[0], w.A[1], w.A[2], w.A[3]};
-    void *const B[4] = {w.B[0], w.B[1], w.B[2], w.B[3]};
-    void *const *src[3] = {U, A, B};
-    void *const *dst[3] = {A, B, U};
-    // Omega of stage st lives in omega[st & 1]: k_pre writes stage 0's, and
-    // the particle pass after stage st computes stage st + 1's from the
-    // density stage st wrote.
-    const size_t ostride = (size_t)(p.max_particles > 0 ? p.max_particles : 0);
-    const ClusterArgs ca = cluster_args(c, np);
+    const bool full = p.nx % TX == 0 && p.ny % TY == 0;
     for (int st = 0; st < 3; ++st) {
-        for (int i = 0; i < 4; ++i) {
-            a.in[i] = (const T *)src[st][i];
-            a.un[i] = (const T *)U[i];
-            a.out[i] = (T *)dst[st][i];
-        }
-        a.ra = (T)ra[st];
-        a.rb = (T)rb[st];
-        for (int k = 0; k < 2; ++k)
-            for (int i = 0; i < 3; ++i) a.noise[k][i] = noise ? (const T *)w.N[k][3 * st + i] : nullptr;
-        a.amp = w.st->amp[st];
+        const StageArgs<T> a = stage_args<T>(c, st);
         hipEvent_t e0 = prof_event(c), e1 = prof_event(c);
         if (e0) (void)hipEventRecord(e0, s);
 #define IC_STAGE(S, N, F) \
@@ -3042,37 +3252,242 @@ hipError_t step_impl(ic_ctx *c, bool overlap, bool first, bool last) {
         }
         if (np > 0) {
             if (st == 0 && side_part) chk(hipStreamWaitEvent(s, c->ev_part, 0));
-            StagePassArgs<T> sp{};
-            sp.nx = p.nx; sp.ny = p.ny; sp.nz = p.nz; sp.np = np;
-            sp.inv_h3 = 1.0 / (p.h * p.h * p.h);
-            sp.b = rb[st];
-            sp.dt_h = p.dt / p.h;
-            sp.dt = p.dt;
-            sp.V = 8.0 * p.h * p.h * p.h;
-            sp.root = ca.root; sp.cnt = ca.cnt; sp.off = ca.off; sp.list = ca.list;
-            sp.bc = w.pk.bc; sp.bf = w.pk.bf; sp.wc = w.pk.wc; sp.wf = w.pk.wf;
-            sp.F = w.F;
-            sp.omega = w.omega + (st & 1) * ostride;
-            sp.eps = w.eps;
-            sp.omega_next = st < 2 ? w.omega + ((st + 1) & 1) * ostride : nullptr;
-            sp.drho_next = (const T *)dst[st][0];
-            for (int i = 0; i < 3; ++i) sp.g[i] = (T *)dst[st][1 + i];
-            hipLaunchKernelGGL(k_cl_stage<T>, dim3(wave_blocks(np)), dim3(256), 0, s, sp);
+            hipLaunchKernelGGL(k_cl_stage<T>, dim3(wave_blocks(np)), dim3(256), 0, s,
+                               stage_pass_args<T>(c, st));
         }
     }
-
-    if (np > 0) {
-        PostPassArgs<T> pp{};
-        pp.pa = pa;
-        pp.root = ca.root; pp.cnt = ca.cnt; pp.off = ca.off; pp.list = ca.list;
-        for (int i = 0; i < 3; ++i) pp.g[i] = (T *)U[1 + i];
-        pp.inv_h3 = 1.0 / (p.h * p.h * p.h);
-        hipLaunchKernelGGL(k_cl_post<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pp);
-    }
+    if (np > 0)
+        hipLaunchKernelGGL(k_cl_post<T>, dim3(wave_blocks(np)), dim3(256), 0, s, post_args<T>(c));
     if (ahead) chk(hipStreamWaitEvent(s, c->ev_noise, 0));
     chk(hipGetLastError());
     return err;
 }
+
+// ---------------------------------------------------------------------------
+// Batched ensemble step: for n contexts of one precision, every kernel of the
+// step runs once for all of them, with per-context arguments in device
+// tables and per-block (or per-wave) maps to the context and its tile (or
+// particle).  Stage and noise tiles are ordered so that each XCD gets a
+// contiguous run of tiles, as in the single-context launches.  Each context
+// draws its own noise every step (as a single-stream step does), so a batched
+// step is bitwise the single-stream step of every member.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct BatchTables {
+    int n = 0;
+    StepState **st = nullptr;
+    DriveArgs *drive = nullptr;
+    NoiseArgs<T> *noise = nullptr;
+    int32_t *nmember = nullptr, *ntile = nullptr;
+    int nnoise = 0;
+    StageArgs<T> *stage[3] = {nullptr, nullptr, nullptr};
+    int32_t *tmember = nullptr, *ttile = nullptr;
+    int ntiles = 0;
+    PartArgs<T> *part = nullptr;
+    ClusterSmallArgs *clus = nullptr;
+    int nclus = 0;
+    StagePassArgs<T> *pass[3] = {nullptr, nullptr, nullptr};
+    PostPassArgs<T> *post = nullptr;
+    int32_t *wmember = nullptr, *wlocal = nullptr;
+    int nwaves = 0;
+};
+
+// Host image of the tables, laid out in one buffer and copied to the device.
+struct TableImage {
+    std::vector<char> bytes;
+    template <typename X>
+    size_t put(const std::vector<X> &v) {
+        const size_t off = (bytes.size() + 255) & ~(size_t)255;
+        bytes.resize(off + v.size() * sizeof(X));
+        if (!v.empty()) memcpy(bytes.data() + off, v.data(), v.size() * sizeof(X));
+        return off;
+    }
+};
+
+inline int host_xcd_tile(int b, int nblk) {
+    const int per = nblk / 8, rem = nblk % 8, xcd = b % 8, idx = b / 8;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+// Block -> (member, tile) for n members of cnt[m] tiles each, XCD-ordered.
+inline void tile_map(const std::vector<int> &cnt, std::vector<int32_t> &member,
+                     std::vector<int32_t> &tile) {
+    std::vector<int> start(cnt.size() + 1, 0);
+    for (size_t m = 0; m < cnt.size(); ++m) start[m + 1] = start[m] + cnt[m];
+    const int total = start.back();
+    member.resize(total);
+    tile.resize(total);
+    for (int g = 0; g < total; ++g) {
+        const int t = host_xcd_tile(g, total);
+        const int m = (int)(std::upper_bound(start.begin(), start.end(), t) - start.begin()) - 1;
+        member[g] = m;
+        tile[g] = t - start[m];
+    }
+}
+
+template <typename T>
+hipError_t batch_build(ic_ctx *const *ctxs, int n, BatchTables<T> &bt, void **dev) {
+    *dev = nullptr;
+    TableImage img;
+    std::vector<StepState *> st;
+    std::vector<DriveArgs> drive;
+    std::vector<NoiseArgs<T>> noise;
+    std::vector<int> ncnt, tcnt;
+    std::vector<StageArgs<T>> stage[3];
+    std::vector<PartArgs<T>> part;
+    std::vector<ClusterSmallArgs> clus;
+    std::vector<StagePassArgs<T>> pass[3];
+    std::vector<PostPassArgs<T>> post;
+    std::vector<int32_t> wmember, wlocal;
+    for (int i = 0; i < n; ++i) {
+        ic_ctx *c = ctxs[i];
+        st.push_back(c->ws.st);
+        drive.push_back(drive_args(c));
+        const NoiseArgs<T> na = noise_args<T>(c);
+        noise.push_back(na);
+        ncnt.push_back(c->p.kT > 0.0 ? na.gx * na.gy * na.gz : 0);
+        tcnt.push_back(c->nblk[0] * c->nblk[1] * c->nblk[2]);
+        for (int s = 0; s < 3; ++s) stage[s].push_back(stage_args<T>(c, s));
+        if (c->np > 0) {
+            const int m = (int)part.size();
+            void *U[4] = {c->f[0], c->f[1], c->f[2], c->f[3]};
+            part.push_back(part_args<T>(c, U));
+            clus.push_back(ClusterSmallArgs{cluster_args(c, c->np), c->ws.pk.bc, c->p.nx, c->p.ny,
+                                            c->p.nz});
+            for (int s = 0; s < 3; ++s) pass[s].push_back(stage_pass_args<T>(c, s));
+            post.push_back(post_args<T>(c));
+            for (int p = 0; p < c->np; ++p) {
+                wmember.push_back(m);
+                wlocal.push_back(p);
+            }
+        }
+    }
+    std::vector<int32_t> nmember, ntile, tmember, ttile;
+    tile_map(ncnt, nmember, ntile);
+    tile_map(tcnt, tmember, ttile);
+    const size_t o_st = img.put(st), o_drive = img.put(drive), o_noise = img.put(noise);
+    const size_t o_nm = img.put(nmember), o_nt = img.put(ntile);
+    size_t o_stage[3], o_pass[3];
+    for (int s = 0; s < 3; ++s) o_stage[s] = img.put(stage[s]);
+    const size_t o_tm = img.put(tmember), o_tt = img.put(ttile);
+    const size_t o_part = img.put(part), o_clus = img.put(clus);
+    for (int s = 0; s < 3; ++s) o_pass[s] = img.put(pass[s]);
+    const size_t o_post = img.put(post), o_wm = img.put(wmember), o_wl = img.put(wlocal);
+    char *d = nullptr;
+    hipError_t e = hipMalloc((void **)&d, img.bytes.size());
+    if (e != hipSuccess) return e;
+    e = hipMemcpy(d, img.bytes.data(), img.bytes.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return e;
+    }
+    *dev = d;
+    bt.n = n;
+    bt.st = (StepState **)(d + o_st);
+    bt.drive = (DriveArgs *)(d + o_drive);
+    bt.noise = (NoiseArgs<T> *)(d + o_noise);
+    bt.nmember = (int32_t *)(d + o_nm);
+    bt.ntile = (int32_t *)(d + o_nt);
+    bt.nnoise = (int)nmember.size();
+    for (int s = 0; s < 3; ++s) {
+        bt.stage[s] = (StageArgs<T> *)(d + o_stage[s]);
+        bt.pass[s] = (StagePassArgs<T> *)(d + o_pass[s]);
+    }
+    bt.tmember = (int32_t *)(d + o_tm);
+    bt.ttile = (int32_t *)(d + o_tt);
+    bt.ntiles = (int)tmember.size();
+    bt.part = (PartArgs<T> *)(d + o_part);
+    bt.clus = (ClusterSmallArgs *)(d + o_clus);
+    bt.nclus = (int)clus.size();
+    bt.post = (PostPassArgs<T> *)(d + o_post);
+    bt.wmember = (int32_t *)(d + o_wm);
+    bt.wlocal = (int32_t *)(d + o_wl);
+    bt.nwaves = (int)wmember.size();
+    return hipSuccess;
+}
+
+// A device pointer to a table as a constant-address-space pointer.
+template <typename X>
+inline const IC_CONST X *cst(const X *p) {
+    return (const IC_CONST X *)(uintptr_t)p;
+}
+
+template <typename T>
+hipError_t batch_step(const BatchTables<T> &bt, hipStream_t s) {
+    hipLaunchKernelGGL(k_step_begin_batched, dim3(bt.n), dim3(64), 0, s, cst(bt.st), cst(bt.drive));
+    if (bt.nnoise > 0)
+        hipLaunchKernelGGL(noise_kernel_batched<T>, dim3(bt.nnoise), dim3(NOISE_THREADS<T>), 0, s,
+                           cst(bt.noise), cst(bt.nmember), cst(bt.ntile));
+    const WaveMap wm{cst(bt.wmember), cst(bt.wlocal), bt.nwaves};
+    if (bt.nwaves > 0) {
+        hipLaunchKernelGGL(k_pre_batched<T>, dim3(wave_blocks(bt.nwaves)), dim3(256), 0, s,
+                           cst(bt.part), wm);
+        hipLaunchKernelGGL(k_cl_small_batched, dim3(bt.nclus), dim3(1024), 0, s, cst(bt.clus));
+    }
+    for (int st = 0; st < 3; ++st) {
+        const dim3 g(bt.ntiles), b(STAGE_THREADS);
+        if (st == 0)
+            hipLaunchKernelGGL((stage_kernel_batched<T, 0>), g, b, 0, s, cst(bt.stage[0]),
+                               cst(bt.tmember), cst(bt.ttile));
+        else if (st == 1)
+            hipLaunchKernelGGL((stage_kernel_batched<T, 1>), g, b, 0, s, cst(bt.stage[1]),
+                               cst(bt.tmember), cst(bt.ttile));
+        else
+            hipLaunchKernelGGL((stage_kernel_batched<T, 2>), g, b, 0, s, cst(bt.stage[2]),
+                               cst(bt.tmember), cst(bt.ttile));
+        if (bt.nwaves > 0)
+            hipLaunchKernelGGL(k_cl_stage_batched<T>, dim3(wave_blocks(bt.nwaves)), dim3(256), 0, s,
+                               cst(bt.pass[st]), wm);
+    }
+    if (bt.nwaves > 0)
+        hipLaunchKernelGGL(k_cl_post_batched<T>, dim3(wave_blocks(bt.nwaves)), dim3(256), 0, s,
+                           cst(bt.post), wm);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+struct Batch {
+    int prec = 0;
+    void *dev = nullptr;
+    BatchTables<float> f;
+    BatchTables<double> d;
+};
+
+bool batch_supported(ic_ctx *const *ctxs, int n) {
+    for (int i = 0; i < n; ++i) {
+        if (ctxs[i]->p.prec != ctxs[0]->p.prec) return false;
+        if (ctxs[i]->np > CL_SMALL_CAP) return false;
+    }
+    return n > 0;
+}
+
+hipError_t batch_create(ic_ctx *const *ctxs, int n, Batch **out) {
+    *out = nullptr;
+    Batch *b = new (std::nothrow) Batch();
+    if (!b) return hipErrorOutOfMemory;
+    b->prec = ctxs[0]->p.prec;
+    const hipError_t e = b->prec == IC_FP64 ? batch_build<double>(ctxs, n, b->d, &b->dev)
+                                            : batch_build<float>(ctxs, n, b->f, &b->dev);
+    if (e != hipSuccess) {
+        delete b;
+        return e;
+    }
+    *out = b;
+    return hipSuccess;
+}
+
+hipError_t batch_step(const Batch *b, hipStream_t s) {
+    return b->prec == IC_FP64 ? batch_step<double>(b->d, s) : batch_step<float>(b->f, s);
+}
+
+void batch_destroy(Batch *b) {
+    if (!b) return;
+    if (b->dev) (void)hipFree(b->dev);
+    delete b;
+}
+
+namespace {
 
 template <typename T>
 hipError_t interp_impl(ic_ctx *c, int n, const double *q, int kind, const void *field,

@@ -184,6 +184,14 @@ int nblocks_of(const ic_ctx *c);            // at the context's z extent
 hipError_t launch_step(ic_ctx *c, bool overlap, bool first, bool last);
 hipError_t launch_interpolate(ic_ctx *c, int n, const double *q, int kind, const void *field,
                               double *out);
+// Batched ensemble steps (ic_graph_create): every kernel of a step runs once
+// for all n contexts.  Supported when the contexts share a precision and
+// none holds more particles than one workgroup clusters (512).
+struct Batch;
+bool batch_supported(ic_ctx *const *ctxs, int n);
+hipError_t batch_create(ic_ctx *const *ctxs, int n, Batch **out);   // device tables (hipMalloc)
+hipError_t batch_step(const Batch *b, hipStream_t s);              // one step of every context
+void batch_destroy(Batch *b);
 // ic_interpolate_noalloc: positions / results in host memory (flags false)
 // are staged through the library's static device buffer; synchronises the
 // context stream.  n <= IC_NOALLOC_MAX_POINTS.

@@ -8,9 +8,12 @@ single `Ensemble.run` launch advances all of them and the chains run
 concurrently on the GPU.  Small grids cannot fill the chip alone; together
 they can.
 
-`autotune_tile` is the tile-shape tuner: for each grid shape it times the
-step at every allowed z extent of the stage tile (4, 8, 16, 32 planes) and
-keeps the fastest.  Results are cached per (grid, precision, particles).
+`autotune_tile` is the tile-shape tuner for a context stepped on its own: for
+each grid shape it times the step at every allowed z extent of the stage
+tile (4, 8, 16, 32 planes) and keeps the fastest.  Results are cached per
+(grid, precision, particles).  `Ensemble.tune_batch` tunes the extent for the
+batched graph instead, where the members together fill the GPU: it times
+graph replays with one extent for every member and keeps the fastest.
 """
 from __future__ import annotations
 
@@ -75,6 +78,31 @@ class Ensemble:
     @property
     def cells(self):
         return sum(w.fluid.nx * w.fluid.ny * w.fluid.nz for w in self.workloads)
+
+    def tune_batch(self, nsteps=10, replays=3):
+        """Stage-tile z extent for the batched graph: the same extent for
+        every member, the one whose graph replays run fastest.  The steps
+        taken while timing advance the members (callers tune before their
+        measured or compared steps)."""
+        import torch
+        best, best_t = None, float("inf")
+        for tz in TILE_CHOICES:
+            for s in self.sims:
+                s.set_tile(tz)
+            self.capture(nsteps)
+            self.run()
+            self.synchronize()
+            t0 = time.perf_counter()
+            self.run(replays)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            if t < best_t:
+                best, best_t = tz, t
+        for s in self.sims:
+            s.set_tile(best)
+        self.tiles = [best] * len(self.sims)
+        self.release()
+        return best
 
     def capture(self, nsteps):
         self.release()
