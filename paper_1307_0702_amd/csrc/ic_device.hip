@@ -9,15 +9,16 @@
 //
 // The fluid stage (the hot loop, three sweeps per step) is one kernel per RK
 // stage: each block owns a TX x TY column of cells and marches it along z,
-// keeping three planes of density, two of momentum and velocity and one of
-// fluxes in LDS.  Every value is read from HBM once per sweep (plus a ring
-// one or two cells wide), the next plane is prefetched into registers while
-// the current one is computed, and every flux and random number is computed
-// once (plus a one-cell ring of halo fluxes).  Random numbers are drawn
-// in-kernel from a counter-based Philox generator keyed by (seed; cell, step,
-// call, replica).  Particle terms enter through per-block candidate lists
-// built once per step and sorted by plane.  There are no float atomics, so
-// results are bitwise reproducible.
+// keeping one plane of momentum, velocity and fluxes and two of density in
+// LDS.  Every value is read from HBM once per sweep (plus a ring one or two
+// cells wide), the next plane is prefetched into registers while the current
+// one is computed, and every flux is computed once (plus a one-cell ring of
+// halo fluxes).  The stochastic increments of a step are drawn once, by the
+// noise kernel, from a counter-based Philox generator keyed by (seed; cell,
+// step, call, replica), and each stage reads its combination.  The particle
+// terms run as one wave per cluster of particles whose kernels may touch the
+// same points, members in ascending id.  There are no float atomics in the
+// forward step, so its results are bitwise reproducible.
 #include <math.h>
 
 #include <algorithm>
@@ -1106,48 +1107,6 @@ __global__ __launch_bounds__(256) void k_weights(const Grid G, int np, const dou
     }
 }
 
-// Omega_p = eps_p V J_p(rho - rho0) for the input density of RK stages 2 and 3
-// (Sec. III, Eq. omega; stage pressures of App. A); stage 1's comes from k_pre.
-template <typename T>
-__global__ __launch_bounds__(256) void k_omega(const PartArgs<T> a, const T *drho) {
-    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (p >= a.np) return;
-    const int lane = threadIdx.x & 63;
-    double s = 0.0;
-    if (lane < 27) {
-        const int d[3] = {lane % 3, (lane / 3) % 3, lane / 9};
-        const int x = wrap(a.bc[3 * p] + d[0], a.G.nx), y = wrap(a.bc[3 * p + 1] + d[1], a.G.ny),
-                  z = wrap(a.bc[3 * p + 2] + d[2], a.G.nz);
-        const double w = a.wc[9 * p + d[0]] * a.wc[9 * p + 3 + d[1]] * a.wc[9 * p + 6 + d[2]];
-        s = w * (double)drho[((size_t)z * a.G.ny + y) * a.G.nx + x];
-    }
-    s = wave_sum(s);
-    if (lane == 0) a.omega[p] = a.eps[p] * a.V * s;
-}
-
-// Substeps 4-5 on the unconstrained state: V~ = J v~, m_f = V J rho_face,
-// u^{n+1} = u^n + m_f/(m_e+m_f) (V~ - u^n); keeps du = V (u^{n+1} - V~).
-template <typename T>
-__global__ __launch_bounds__(256) void k_post(const PartArgs<T> a) {
-    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (p >= a.np) return;
-    const int lane = threadIdx.x & 63;
-    const double qh[3] = {a.qh[3 * p], a.qh[3 * p + 1], a.qh[3 * p + 2]};
-    double Vt[3], sm[3];
-    wave_face_sums<T>(a.G, a.f, qh, Vt, sm);
-    if (lane < 3) {
-        const int ax = lane;
-        const double me = a.me[p];
-        const double mf = a.V * sm[ax];
-        if (!(me + mf > 0.0)) a.flag[0] = 1;
-        const double u = a.u[3 * p + ax];
-        const double un = u + mf / (me + mf) * (Vt[ax] - u);
-        a.Vt[3 * p + ax] = un;  // u^{n+1}
-        a.du[3 * p + ax] = a.V * (un - Vt[ax]);
-        a.mf[3 * p + ax] = mf;
-    }
-}
-
 // u := J v at the particle positions (no-slip initial velocity).
 template <typename T>
 __global__ __launch_bounds__(256) void k_init_u(const PartArgs<T> a) {
@@ -1481,47 +1440,31 @@ __global__ __launch_bounds__(SB_THREADS) void k_bin_small(const BinArgs b) {
     }
 }
 
-// Sparse owner-computes updates of the grid near particles, one stage block
-// per workgroup.  The block's candidates arrive ordered by (colour, id) from
-// k_bin_sort; candidates of one colour touch disjoint points, so each colour
-// is one parallel round over (candidate, point) items and every point
-// receives its sums in the same order on every run (no float atomics).
-// Modes:
-//   SP_SPREAD : field += f_p w_p / h^3 (caller spreading, one location kind)
-//   SP_NOSLIP : g^a += rho_face V w_a (u^{n+1} - V~)^a / h^3 (substep 6)
-//   SP_STAGE  : g^a += b [-(dt/h) (P(i+a) - P(i)) + dt F^a w_a / h^3] with
-//               P = Omega w / h^3, the particle pressure and the spread
-//               external force of one RK stage (App. A, stage pressures).
-enum { SP_SPREAD = 0, SP_NOSLIP = 1, SP_STAGE = 2 };
-
+// Spreading S of caller values onto one field (ic_spread), owner-computes,
+// one stage block per workgroup.  The block's candidates arrive ordered by
+// (colour, id) from k_bin_sort; candidates of one colour touch disjoint
+// points, so each colour is one parallel round over (candidate, point) items
+// and every point receives its sums in the same order on every run (no float
+// atomics): field += f_p w_p / h^3 over the 27 points of one location kind.
 template <typename T>
 struct SparseArgs {
     int nx, ny, nz, tz;
-    double inv_h3, rho0, b, dt_h, dt;
+    double inv_h3;
     const int32_t *blk_off, *blk_list, *blk_color, *bc, *bf;
     const double *wc, *wf;
-    const double *val;   // SPREAD: f[p]; NOSLIP: du[p][3]; STAGE: F[p][3]
-    const double *omega; // STAGE only
-    // STAGE only, optional: Omega of the next stage, eps V J(drho_next) with
-    // drho_next the density this stage wrote, computed by the block whose
-    // tile holds the particle's nearest cell (nullptr: not computed)
-    double *omega_next;
-    const T *drho_next;
-    const double *eps;
-    double V;
-    int kind;            // SPREAD only
-    T *fields[3];
-    const T *drho;       // NOSLIP only
+    const double *val;   // f[p]
+    int kind;            // IC_CELL or IC_FACE_*
+    T *field;
 };
 
 constexpr int SP_CAP = 64;    // candidates staged in LDS at a time
 constexpr int SP_THREADS = 256;   // threads of a sparse block (one stage tile)
 constexpr int SP_BATCH = 4;   // items per thread whose loads are issued together
 
-template <typename T, int MODE>
+template <typename T>
 __global__ __launch_bounds__(SP_THREADS) void k_sparse(const SparseArgs<T> a) {
-    __shared__ int32_t s_bc[SP_CAP][3], s_bf[SP_CAP][3], s_col[SP_CAP], s_pid[SP_CAP];
-    __shared__ double s_wc[SP_CAP][9], s_wf[SP_CAP][9], s_v[SP_CAP][4];
+    __shared__ int32_t s_bc[SP_CAP][3], s_bf[SP_CAP][3], s_col[SP_CAP];
+    __shared__ double s_wc[SP_CAP][9], s_wf[SP_CAP][9], s_v[SP_CAP];
     const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     const int cb = a.blk_off[blk], ce = a.blk_off[blk + 1];
     if (cb == ce) return;
@@ -1531,16 +1474,14 @@ __global__ __launch_bounds__(SP_THREADS) void k_sparse(const SparseArgs<T> a) {
     const int lo[3] = {x0, y0, z0};
     const int wd[3] = {min(TX, nx - x0), min(TY, ny - y0), min(a.tz, nz - z0)};
     const int tid = threadIdx.x;
-    constexpr int ncomp = MODE == SP_SPREAD ? 1 : 3;
-    constexpr int per_comp = MODE == SP_STAGE ? 36 : 27;
-    constexpr int per = ncomp * per_comp;
+    const int fa = a.kind - 1;   // face axis, -1: cells
+    constexpr int per = 27;
 
     for (int c0 = cb; c0 < ce; c0 += SP_CAP) {
         const int nc = min(SP_CAP, ce - c0);
         __syncthreads();
         for (int i = tid; i < nc; i += SP_THREADS) {
             const int pid = a.blk_list[c0 + i];
-            s_pid[i] = pid;
             s_col[i] = a.blk_color[c0 + i];
             for (int d = 0; d < 3; ++d) {
                 s_bc[i][d] = a.bc[3 * pid + d];
@@ -1550,12 +1491,7 @@ __global__ __launch_bounds__(SP_THREADS) void k_sparse(const SparseArgs<T> a) {
                 s_wc[i][d] = a.wc[9 * pid + d];
                 s_wf[i][d] = a.wf[9 * pid + d];
             }
-            if (MODE == SP_SPREAD) {
-                s_v[i][0] = a.val[pid];
-            } else {
-                for (int d = 0; d < 3; ++d) s_v[i][d] = a.val[3 * pid + d];
-                s_v[i][3] = MODE == SP_STAGE ? a.omega[pid] : 0.0;
-            }
+            s_v[i] = a.val[pid];
         }
         __syncthreads();
         for (int r0 = 0; r0 < nc;) {
@@ -1567,7 +1503,6 @@ __global__ __launch_bounds__(SP_THREADS) void k_sparse(const SparseArgs<T> a) {
             for (int base = 0; base < items; base += SP_BATCH * SP_THREADS) {
                 size_t gi[SP_BATCH];
                 double add[SP_BATCH];
-                int cmp[SP_BATCH];
                 bool ok[SP_BATCH];
 #pragma unroll
                 for (int bi = 0; bi < SP_BATCH; ++bi) {
@@ -1575,116 +1510,41 @@ __global__ __launch_bounds__(SP_THREADS) void k_sparse(const SparseArgs<T> a) {
                     ok[bi] = false;
                     gi[bi] = 0;
                     add[bi] = 0.0;
-                    cmp[bi] = 0;
                     if (it >= items) continue;
                     const int cq = it / per;
                     const int ci = r0 + cq;
-                    const int item = it - cq * per;
-                    const int comp = MODE == SP_SPREAD ? 0 : item / per_comp;
-                    const int pt = item - comp * per_comp;
-                    const int fa = MODE == SP_SPREAD ? a.kind - 1 : comp;  // face axis, -1: cells
-                    // point index along each axis relative to the box start;
-                    // SP_STAGE boxes span 4 points along the face axis
-                    int d[3];
-                    if (MODE == SP_STAGE && fa == 0) {
-                        d[0] = pt % 4; d[1] = (pt / 4) % 3; d[2] = pt / 12;
-                    } else if (MODE == SP_STAGE && fa == 1) {
-                        d[0] = pt % 3; d[1] = (pt / 3) % 4; d[2] = pt / 12;
-                    } else {
-                        d[0] = pt % 3; d[1] = (pt / 3) % 3; d[2] = pt / 9;
-                    }
+                    const int pt = it - cq * per;
+                    // point index along each axis relative to the stencil start
+                    const int d[3] = {pt % 3, (pt / 3) % 3, pt / 9};
                     int pos[3];
                     bool in = true;
 #pragma unroll
                     for (int ax = 0; ax < 3; ++ax) {
-                        int start;
-                        if (MODE == SP_STAGE)
-                            start = s_bc[ci][ax] - (ax == fa ? 1 : 0);
-                        else
-                            start = ax == fa ? s_bf[ci][ax] : s_bc[ci][ax];
+                        const int start = ax == fa ? s_bf[ci][ax] : s_bc[ci][ax];
                         pos[ax] = wrap(start + d[ax], n[ax]);
                         in = in && pos[ax] >= lo[ax] && pos[ax] < lo[ax] + wd[ax];
                     }
                     if (!in) continue;
-                    const size_t g = ((size_t)pos[2] * ny + pos[1]) * nx + pos[0];
-                    // Weights from the point offsets relative to the stencil
-                    // starts: cell weights
-                    // wc[ax][d] on the axes other than the face axis, which
-                    // are shared by every weight of the item.
+                    // cell weights on the axes other than the face axis
                     double po = 1.0;
 #pragma unroll
                     for (int ax = 0; ax < 3; ++ax)
                         if (ax != fa) po *= s_wc[ci][3 * ax + d[ax]];
-                    double v;
-                    if (MODE == SP_SPREAD) {
-                        const double w = fa < 0 ? po : po * s_wf[ci][3 * fa + d[fa]];
-                        v = s_v[ci][0] * w * a.inv_h3;
-                    } else if (MODE == SP_NOSLIP) {
-                        int nb[3] = {pos[0], pos[1], pos[2]};
-                        nb[fa] = nb[fa] + 1 == n[fa] ? 0 : nb[fa] + 1;
-                        const size_t j = ((size_t)nb[2] * ny + nb[1]) * nx + nb[0];
-                        const double rf = a.rho0 + 0.5 * ((double)a.drho[g] + (double)a.drho[j]);
-                        v = rf * s_v[ci][comp] * (po * s_wf[ci][3 * fa + d[fa]]) * a.inv_h3;
-                    } else {
-                        // along the face axis the box runs bc-1 .. bc+2: the cell
-                        // at pos has offset d-1, the next cell d, the face
-                        // d - 1 + (bc - bf) in its own stencil (bc - bf is 0 or
-                        // 1 up to the period)
-                        const int dc = d[fa];
-                        int sh = s_bc[ci][fa] - s_bf[ci][fa];   // starts are stored wrapped
-                        if (sh < 0) sh += n[fa];
-                        const int of = dc - 1 + sh;
-                        const double w_pos = dc >= 1 ? po * s_wc[ci][3 * fa + dc - 1] : 0.0;
-                        const double w_nb = dc <= 2 ? po * s_wc[ci][3 * fa + dc] : 0.0;
-                        const double w_f = (of >= 0 && of <= 2) ? po * s_wf[ci][3 * fa + of] : 0.0;
-                        const double om = s_v[ci][3];
-                        const double dP = om * (w_nb - w_pos) * a.inv_h3;
-                        const double fw = s_v[ci][comp] * w_f * a.inv_h3;
-                        v = a.b * (-a.dt_h * dP + a.dt * fw);
-                    }
+                    const double w = fa < 0 ? po : po * s_wf[ci][3 * fa + d[fa]];
                     ok[bi] = true;
-                    gi[bi] = g;
-                    add[bi] = v;
-                    cmp[bi] = comp;
+                    gi[bi] = ((size_t)pos[2] * ny + pos[1]) * nx + pos[0];
+                    add[bi] = s_v[ci] * w * a.inv_h3;
                 }
                 // the batch's points are distinct: issue every load, then every store
                 T old[SP_BATCH];
 #pragma unroll
-                for (int bi = 0; bi < SP_BATCH; ++bi)
-                    old[bi] = ok[bi] ? a.fields[cmp[bi]][gi[bi]] : (T)0;
+                for (int bi = 0; bi < SP_BATCH; ++bi) old[bi] = ok[bi] ? a.field[gi[bi]] : (T)0;
 #pragma unroll
                 for (int bi = 0; bi < SP_BATCH; ++bi)
-                    if (ok[bi]) a.fields[cmp[bi]][gi[bi]] = (T)((double)old[bi] + add[bi]);
+                    if (ok[bi]) a.field[gi[bi]] = (T)((double)old[bi] + add[bi]);
             }
             __syncthreads();
             r0 = r1;
-        }
-        if (MODE == SP_STAGE && a.omega_next) {
-            // Omega of the next stage for the candidates whose nearest cell
-            // is in this tile (one block per particle), one wave each: the
-            // same 27 products and butterfly sum as k_omega
-            const int lane = tid & 63, wave = tid >> 6;
-            int owned = 0;
-            for (int i = 0; i < nc; ++i) {
-                bool mine = true;
-#pragma unroll
-                for (int ax = 0; ax < 3; ++ax) {
-                    const int cc = wrap(s_bc[i][ax] + 1, n[ax]);
-                    mine = mine && cc >= lo[ax] && cc < lo[ax] + wd[ax];
-                }
-                if (!mine) continue;
-                if (owned++ % (SP_THREADS / 64) != wave) continue;
-                double v = 0.0;
-                if (lane < 27) {
-                    const int d0 = lane % 3, d1 = (lane / 3) % 3, d2 = lane / 9;
-                    const int x = wrap(s_bc[i][0] + d0, nx), y = wrap(s_bc[i][1] + d1, ny),
-                              z = wrap(s_bc[i][2] + d2, nz);
-                    const double w = s_wc[i][d0] * s_wc[i][3 + d1] * s_wc[i][6 + d2];
-                    v = w * (double)a.drho_next[((size_t)z * ny + y) * nx + x];
-                }
-                v = wave_sum(v);
-                if (lane == 0) a.omega_next[s_pid[i]] = a.eps[s_pid[i]] * a.V * v;
-            }
         }
     }
 }
@@ -1958,7 +1818,7 @@ __device__ __forceinline__ void member_fence() {
 // each particle, g^a += b [-(dt/h) (P(i+a) - P(i)) + dt F^a w_a / h^3] with
 // P = Omega w / h^3, over the 4 x 3 x 3 faces of each component its pressure
 // and force reach; and the next stage's Omega = eps V J(drho_next) from the
-// density this stage wrote (the same 27 products and butterfly as k_omega).
+// density this stage wrote (27 products in the lanes, a butterfly sum).
 template <typename T>
 struct StagePassArgs {
     int nx, ny, nz, np;
@@ -2085,12 +1945,14 @@ __global__ __launch_bounds__(256) void k_cl_stage_batched(const IC_CONST StagePa
 }
 
 // Substeps 4-7 for one cluster per wave (App. A): the impulse and particle
-// velocity of every member from the unconstrained state (as k_post), then
-// the momentum-conserving corrections member after member (as k_sparse in
-// no-slip mode), then the full-step positions q^{n+1} = q^n + dt/2
+// velocity of every member from the unconstrained state, V~ = J v~,
+// m_f = V J rho_face, u^{n+1} = u^n + m_f/(m_e + m_f) (V~ - u^n); then the
+// momentum-conserving corrections g += rho_face V S(u^{n+1} - V~) member
+// after member; then the full-step positions q^{n+1} = q^n + dt/2
 // J^{n+1/2}(v^{n+1} + v^n) and the window sums from the corrected state.
-// Reading R6: every member's V~ comes from the uncorrected state.  A non-finite V~, m_f or position raises flag[2]
-// (and the position keeps its old value); m_e + m_f <= 0 raises flag[0].
+// Reading R6: every member's V~ comes from the uncorrected state.  A
+// non-finite V~, m_f or position raises flag[2] (and the position keeps its
+// old value); m_e + m_f <= 0 raises flag[0].
 template <typename T>
 struct PostPassArgs {
     PartArgs<T> pa;
@@ -2203,7 +2065,9 @@ __device__ __forceinline__ void final_of(const PartArgs<T> &a, int p) {
     }
 }
 
-template <typename T>
+// FINAL = false: substeps 4-6 only (the reverse mode's recomputation, which
+// keeps positions and window sums untouched).
+template <typename T, bool FINAL = true>
 __device__ __forceinline__ void cl_post_body(const PostPassArgs<T> &c, int p) {
     const PartArgs<T> &a = c.pa;
     if (c.root[p] != p) return;
@@ -2222,6 +2086,7 @@ __device__ __forceinline__ void cl_post_body(const PostPassArgs<T> &c, int p) {
         noslip_of(c, m);
         member_fence();
     }
+    if (!FINAL) return;
     m = p;
     for (int i = 0; i < k; ++i) {
         if (i) m = cluster_next(c.list, o, k, m);
@@ -2234,6 +2099,13 @@ __global__ __launch_bounds__(256) void k_cl_post(const PostPassArgs<T> c) {
     const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (p >= c.pa.np) return;
     cl_post_body(c, p);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cl_noslip(const PostPassArgs<T> c) {
+    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (p >= c.pa.np) return;
+    cl_post_body<T, false>(c, p);
 }
 
 template <typename T>
@@ -3032,20 +2904,6 @@ void launch_clusters(ic_ctx *c, int np, hipStream_t s) {
     hipLaunchKernelGGL(k_cl_fill, dim3(thread_blocks(np)), dim3(256), 0, s, ca);
 }
 
-template <typename T>
-SparseArgs<T> sparse_args(ic_ctx *c) {
-    const ic_params &p = c->p;
-    const Workspace &w = c->ws;
-    SparseArgs<T> sa{};
-    sa.nx = p.nx; sa.ny = p.ny; sa.nz = p.nz; sa.tz = c->tz;
-    sa.inv_h3 = 1.0 / (p.h * p.h * p.h);
-    sa.rho0 = p.rho0;
-    sa.dt_h = p.dt / p.h;
-    sa.dt = p.dt;
-    sa.blk_off = w.blk_off; sa.blk_list = w.blk_list; sa.blk_color = w.blk_key;
-    sa.bc = w.pk.bc; sa.bf = w.pk.bf; sa.wc = w.pk.wc; sa.wf = w.pk.wf;
-    return sa;
-}
 
 // Arguments of one context's step kernels (shared by the eager step and the
 // batched ensemble step, so both run the same arithmetic).
@@ -3507,12 +3365,16 @@ hipError_t spread_impl(ic_ctx *c, int n, const double *q, const double *f, int k
     hipLaunchKernelGGL(k_weights, dim3(wave_blocks(n)), dim3(256), 0, c->stream, G, n, q, w.qh,
                        w.pk.bc, w.pk.bf, w.pk.wc, w.pk.wf);
     launch_binning(c, n, w.qh, c->stream);
-    SparseArgs<T> sa = sparse_args<T>(c);
+    SparseArgs<T> sa{};
+    sa.nx = p.nx; sa.ny = p.ny; sa.nz = p.nz; sa.tz = c->tz;
+    sa.inv_h3 = 1.0 / (p.h * p.h * p.h);
+    sa.blk_off = w.blk_off; sa.blk_list = w.blk_list; sa.blk_color = w.blk_key;
+    sa.bc = w.pk.bc; sa.bf = w.pk.bf; sa.wc = w.pk.wc; sa.wf = w.pk.wf;
     sa.val = f;
     sa.kind = kind;
-    sa.fields[0] = (T *)field;
+    sa.field = (T *)field;
     const dim3 grid(c->nblk[0], c->nblk[1], c->nblk[2]);
-    hipLaunchKernelGGL((k_sparse<T, SP_SPREAD>), grid, dim3(SP_THREADS), 0, c->stream, sa);
+    hipLaunchKernelGGL(k_sparse<T>, grid, dim3(SP_THREADS), 0, c->stream, sa);
     return hipGetLastError();
 }
 
@@ -3564,7 +3426,6 @@ hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *con
     const unsigned nblk_all = (unsigned)(c->nblk[0] * c->nblk[1] * c->nblk[2]);
     const bool full = p.nx % TX == 0 && p.ny % TY == 0;
     const int np = pp ? c->np : 0;
-    const dim3 sgrid(c->nblk[0], c->nblk[1], c->nblk[2]);
     // every block of the momentum pass owns one partial-sum slot per mode
     const int atz = adjoint_tz(p);
     if ((long)((p.nx + ATX - 1) / ATX) * ((p.ny + ATY - 1) / ATY) * ((p.nz + atz - 1) / atz) >
@@ -3581,15 +3442,13 @@ hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *con
         pa.u = const_cast<double *>(pp->u);
     }
     // particle terms of recomputed stage st, written into the stage output
+    // dst (and the next stage's Omega from its density)
     auto stage_particles = [&](int st, void *const *dst) {
         if (np == 0) return;
-        SparseArgs<T> sa = sparse_args<T>(c);
-        const double rb[3] = {1.0, 0.25, 2.0 / 3.0};
-        sa.b = rb[st];
-        sa.val = w.F;
-        sa.omega = w.omega;
-        for (int i = 0; i < 3; ++i) sa.fields[i] = (T *)dst[1 + i];
-        hipLaunchKernelGGL((k_sparse<T, SP_STAGE>), sgrid, dim3(SP_THREADS), 0, s, sa);
+        StagePassArgs<T> sp = stage_pass_args<T>(c, st);
+        sp.drho_next = (const T *)dst[0];
+        for (int i = 0; i < 3; ++i) sp.g[i] = (T *)dst[1 + i];
+        hipLaunchKernelGGL(k_cl_stage<T>, dim3(wave_blocks(np)), dim3(256), 0, s, sp);
     };
 
     // stage inputs of step n
@@ -3625,7 +3484,7 @@ hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *con
     }
     if (np > 0) {
         hipLaunchKernelGGL(k_pre<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa);
-        launch_binning(c, np, w.qh, s);
+        launch_clusters(c, np, s);
     }
     a.ra = (T)0.0;
     a.rb = (T)1.0;
@@ -3642,8 +3501,6 @@ hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *con
     a.ra = (T)0.75;
     a.rb = (T)0.25;
     a.amp = w.st->amp[1];
-    if (np > 0)
-        hipLaunchKernelGGL(k_omega<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa, (const T *)w.A[0]);
     if (full)
         hipLaunchKernelGGL((stage_kernel<T, 1, false, true>), dim3(nblk_all), dim3(STAGE_THREADS), 0, s, a);
     else
@@ -3660,7 +3517,6 @@ hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *con
         a.ra = (T)(1.0 / 3.0);
         a.rb = (T)(2.0 / 3.0);
         a.amp = w.st->amp[2];
-        hipLaunchKernelGGL(k_omega<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa, (const T *)w.B[0]);
         if (full)
             hipLaunchKernelGGL((stage_kernel<T, 2, false, true>), dim3(nblk_all), dim3(STAGE_THREADS), 0, s, a);
         else
@@ -3672,13 +3528,13 @@ hipError_t adjoint_impl(ic_ctx *c, int64_t n, const void *const Un[4], void *con
             if (e != hipSuccess) return e;
         }
         for (int i = 0; i < 4; ++i) pa.f[i] = (const T *)aw.L1[i];
-        hipLaunchKernelGGL(k_post<T>, dim3(wave_blocks(np)), dim3(256), 0, s, pa);
         {
-            SparseArgs<T> sa = sparse_args<T>(c);
-            sa.val = w.du;
-            for (int i = 0; i < 3; ++i) sa.fields[i] = (T *)aw.acc[1 + i];
-            sa.drho = (const T *)aw.L1[0];
-            hipLaunchKernelGGL((k_sparse<T, SP_NOSLIP>), sgrid, dim3(SP_THREADS), 0, s, sa);
+            // substeps 4-6: impulse from the third stage output, corrections
+            // into the copy of its momentum
+            PostPassArgs<T> po = post_args<T>(c);
+            po.pa = pa;
+            for (int i = 0; i < 3; ++i) po.g[i] = (T *)aw.acc[1 + i];
+            hipLaunchKernelGGL(k_cl_noslip<T>, dim3(wave_blocks(np)), dim3(256), 0, s, po);
         }
         // substeps 7, 6, 5, 4 reversed
         pr.G = Grid{p.nx, p.ny, p.nz, p.h, 1.0 / p.h, p.rho0};
