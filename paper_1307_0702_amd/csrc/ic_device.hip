@@ -2065,6 +2065,103 @@ __device__ __forceinline__ void final_of(const PartArgs<T> &a, int p) {
     }
 }
 
+// Substeps 4-7 of a particle alone in its cluster: no other particle
+// touches its points, so one gather serves all three phases.  Each lane keeps
+// its face points' index, weight, face density and momentum from the
+// impulse gather, writes the corrected momentum and sums J v^{n+1} from the
+// values it wrote, with the same products and sums as a fresh gather.
+template <typename T, bool FINAL>
+__device__ __forceinline__ void post_single(const PostPassArgs<T> &c, int p) {
+    const PartArgs<T> &a = c.pa;
+    const int lane = threadIdx.x & 63;
+    const double qh[3] = {a.qh[3 * p], a.qh[3 * p + 1], a.qh[3 * p + 2]};
+    const WaveKernel k = wave_kernel(a.G, qh);
+    size_t gi[2];
+    double w[2], rf[2], gt[2];
+    int ax[2];
+    bool ok[2];
+    double av[3] = {0, 0, 0}, am[3] = {0, 0, 0};
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const int item = lane + 64 * it;
+        ok[it] = item < 81;
+        const int itm = ok[it] ? item : 0;
+        ax[it] = itm / 27;
+        size_t j;
+        wave_point(a.G, k, ax[it] + 1, itm % 27, &gi[it], &w[it], ax[it], &j);
+        rf[it] = 0.0;
+        gt[it] = 0.0;
+        if (ok[it]) {
+            rf[it] = a.G.rho0 + 0.5 * ((double)a.f[0][gi[it]] + (double)a.f[0][j]);
+            gt[it] = (double)a.f[1 + ax[it]][gi[it]];
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                if (b == ax[it]) {
+                    av[b] += w[it] * (gt[it] / rf[it]);
+                    am[b] += w[it] * rf[it];
+                }
+        }
+    }
+    double Vt[3], sm[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        Vt[b] = wave_sum(av[b]);
+        sm[b] = wave_sum(am[b]);
+    }
+    // substeps 4-5 (lanes 0-2, one component each)
+    double du = 0.0, un = 0.0;
+    if (lane < 3) {
+        const int b = lane;
+        const double me = a.me[p];
+        const double mf = a.V * sm[b];
+        const double u = a.u[3 * p + b];
+        un = u + mf / (me + mf) * (Vt[b] - u);
+        du = a.V * (un - Vt[b]);
+        if (!isfinite(Vt[b]) || !isfinite(mf)) {
+            a.flag[2] = 1;
+            un = u;
+            du = 0.0;
+        } else if (!(me + mf > 0.0)) {
+            a.flag[0] = 1;
+        }
+        a.Vt[3 * p + b] = un;
+        a.du[3 * p + b] = du;
+        a.mf[3 * p + b] = mf;
+    }
+    // substep 6 on the kept points, then J v^{n+1} from the written values
+    double jvs[3] = {0, 0, 0};
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double dua = __shfl(du, ax[it], 64);
+        if (ok[it]) {
+            const T gn = (T)(gt[it] + rf[it] * dua * w[it] * c.inv_h3);
+            c.g[ax[it]][gi[it]] = gn;
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                if (b == ax[it]) jvs[b] += w[it] * ((double)gn / rf[it]);
+        }
+    }
+    if (!FINAL) return;
+    double jv[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) jv[b] = wave_sum(jvs[b]);
+    if (lane < 3) {
+        const int b = lane;
+        const double q = a.q[3 * p + b];
+        const double qn = q + 0.5 * a.dt * (jv[b] + a.jv_old[3 * p + b]);
+        if (isfinite(qn))
+            a.q[3 * p + b] = wrap_pos(qn, a.L[b]);
+        else
+            a.flag[2] = 1;
+        const double F = a.F[3 * p + b];
+        const double lam = a.me[p] * (un - a.u[3 * p + b]) / a.dt - F;
+        a.sum_f[3 * p + b] += -(F - a.fext[3 * p + b]);
+        a.sum_l[3 * p + b] += lam;
+        a.u[3 * p + b] = un;
+        a.jv_new[3 * p + b] = jv[b];
+    }
+}
+
 // FINAL = false: substeps 4-6 only (the reverse mode's recomputation, which
 // keeps positions and window sums untouched).
 template <typename T, bool FINAL = true>
@@ -2072,6 +2169,10 @@ __device__ __forceinline__ void cl_post_body(const PostPassArgs<T> &c, int p) {
     const PartArgs<T> &a = c.pa;
     if (c.root[p] != p) return;
     const int k = c.cnt[p], o = c.off[p];
+    if (k == 1) {
+        post_single<T, FINAL>(c, p);
+        return;
+    }
     int m = p;
     for (int i = 0; i < k; ++i) {
         if (i) m = cluster_next(c.list, o, k, m);
