@@ -308,9 +308,15 @@ __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, uint3
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
 }
 
+// Kernels on the step's critical path (stage sweeps, particle passes) raise
+// their waves' issue priority, so that the next step's noise kernel, which
+// shares the CUs with them and is ALU-bound, takes the issue slots they leave
+// idle rather than the ones they would use.
+__device__ __forceinline__ void critical_path() { __builtin_amdgcn_s_setprio(3); }
+
 // Imposed pressure at cell (x, y, z).  The particle pressure S Omega and the
-// spread force S F are added after the sweep (k_sparse, stage mode): both
-// enter the stage output linearly.
+// spread force S F are added after the sweep (k_cl_stage): both enter the
+// stage output linearly.
 // Split as p_ext(x, y) + p_ext(z): the x and y parts are fixed for a column,
 // the z part is uniform over a plane.
 template <typename T>
@@ -670,6 +676,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &a, int t, T *lds)
 template <typename T, int STAGE, bool NOISE, bool FULL>
 IC_STAGE_ATTRS void stage_kernel(const StageArgs<T> a) {
     __shared__ T s_lds[STAGE_LDS];
+    critical_path();
     stage_body<T, STAGE, NOISE, FULL>(a, xcd_tile(blockIdx.x, a.gx * a.gy * a.gz), s_lds);
 }
 
@@ -1063,6 +1070,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_pre(const PartArgs<T> a) {
     const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (p >= a.np) return;
+    critical_path();
     pre_body(a, p);
 }
 
@@ -1889,14 +1897,11 @@ __device__ __forceinline__ void stage_terms_of(const StagePassArgs<T> &a, int p)
         add[it] = a.b * (-a.dt_h * dP + a.dt * fw);
         cmp[it] = fa;
     }
-    T old[2];
-#pragma unroll
-    for (int it = 0; it < 2; ++it) old[it] = ok[it] ? a.g[cmp[it]][gi[it]] : (T)0;
-#pragma unroll
-    for (int it = 0; it < 2; ++it)
-        if (ok[it]) a.g[cmp[it]][gi[it]] = (T)((double)old[it] + add[it]);
+    // The next stage's Omega reads the density this stage wrote, which the
+    // particle terms do not change: its gather goes out with the momentum
+    // loads instead of after the stores.
+    double v = 0.0;
     if (a.omega_next) {
-        double v = 0.0;
         const int l27 = lane < 27 ? lane : 0;
         const int d0 = l27 % 3, d1 = (l27 / 3) % 3, d2 = l27 / 9;
         const double w = st_wc(s, 0, d0) * st_wc(s, 1, d1) * st_wc(s, 2, d2);
@@ -1905,6 +1910,14 @@ __device__ __forceinline__ void stage_terms_of(const StagePassArgs<T> &a, int p)
                       z = wrap(bcv[2] + d2, a.nz);
             v = w * (double)a.drho_next[((size_t)z * a.ny + y) * a.nx + x];
         }
+    }
+    T old[2];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) old[it] = ok[it] ? a.g[cmp[it]][gi[it]] : (T)0;
+#pragma unroll
+    for (int it = 0; it < 2; ++it)
+        if (ok[it]) a.g[cmp[it]][gi[it]] = (T)((double)old[it] + add[it]);
+    if (a.omega_next) {
         v = wave_sum(v);
         if (lane == 0) a.omega_next[p] = a.eps[p] * a.V * v;
     }
@@ -1933,6 +1946,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_cl_stage(const StagePassArgs<T> a) {
     const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (p >= a.np) return;
+    critical_path();
     cl_stage_body(a, p);
 }
 
@@ -2075,6 +2089,19 @@ __device__ __forceinline__ void post_single(const PostPassArgs<T> &c, int p) {
     const PartArgs<T> &a = c.pa;
     const int lane = threadIdx.x & 63;
     const double qh[3] = {a.qh[3 * p], a.qh[3 * p + 1], a.qh[3 * p + 2]};
+    // lanes 0-2 load their component's particle state with the position, so
+    // these loads share one round trip instead of following the gathers
+    const int lb = lane < 3 ? lane : 0;
+    const double me = a.me[p], u = a.u[3 * p + lb];
+    double q = 0.0, jvo = 0.0, Fp = 0.0, fx = 0.0, sf = 0.0, sl = 0.0;
+    if (FINAL && lane < 3) {
+        q = a.q[3 * p + lb];
+        jvo = a.jv_old[3 * p + lb];
+        Fp = a.F[3 * p + lb];
+        fx = a.fext[3 * p + lb];
+        sf = a.sum_f[3 * p + lb];
+        sl = a.sum_l[3 * p + lb];
+    }
     const WaveKernel k = wave_kernel(a.G, qh);
     size_t gi[2];
     double w[2], rf[2], gt[2];
@@ -2112,9 +2139,7 @@ __device__ __forceinline__ void post_single(const PostPassArgs<T> &c, int p) {
     double du = 0.0, un = 0.0;
     if (lane < 3) {
         const int b = lane;
-        const double me = a.me[p];
         const double mf = a.V * sm[b];
-        const double u = a.u[3 * p + b];
         un = u + mf / (me + mf) * (Vt[b] - u);
         du = a.V * (un - Vt[b]);
         if (!isfinite(Vt[b]) || !isfinite(mf)) {
@@ -2147,16 +2172,14 @@ __device__ __forceinline__ void post_single(const PostPassArgs<T> &c, int p) {
     for (int b = 0; b < 3; ++b) jv[b] = wave_sum(jvs[b]);
     if (lane < 3) {
         const int b = lane;
-        const double q = a.q[3 * p + b];
-        const double qn = q + 0.5 * a.dt * (jv[b] + a.jv_old[3 * p + b]);
+        const double qn = q + 0.5 * a.dt * (jv[b] + jvo);
         if (isfinite(qn))
             a.q[3 * p + b] = wrap_pos(qn, a.L[b]);
         else
             a.flag[2] = 1;
-        const double F = a.F[3 * p + b];
-        const double lam = a.me[p] * (un - a.u[3 * p + b]) / a.dt - F;
-        a.sum_f[3 * p + b] += -(F - a.fext[3 * p + b]);
-        a.sum_l[3 * p + b] += lam;
+        const double lam = me * (un - u) / a.dt - Fp;
+        a.sum_f[3 * p + b] = sf + -(Fp - fx);
+        a.sum_l[3 * p + b] = sl + lam;
         a.u[3 * p + b] = un;
         a.jv_new[3 * p + b] = jv[b];
     }
@@ -2199,6 +2222,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_cl_post(const PostPassArgs<T> c) {
     const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (p >= c.pa.np) return;
+    critical_path();
     cl_post_body(c, p);
 }
 

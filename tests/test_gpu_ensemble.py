@@ -20,11 +20,15 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-def _members():
+def _members(big=False):
     # uneven grids and particle counts, own seeds and replica ids; one member
-    # driven, one without particles
+    # driven, one without particles.  big: the second member holds 600
+    # particles, above the 512 that one workgroup clusters, so the graph
+    # holds one chain of single-context launches per member instead of the
+    # batched kernels.
     ws = []
-    for r, (nx, ny, nz, npart) in enumerate([(36, 20, 24, 7), (32, 32, 16, 3), (20, 18, 22, 0)]):
+    shapes = [(36, 20, 24, 7), (48, 40, 40, 600) if big else (32, 32, 16, 3), (20, 18, 22, 0)]
+    for r, (nx, ny, nz, npart) in enumerate(shapes):
         w = W.small_random(nx=nx, ny=ny, nz=nz, npart=npart, seed=50 + r, kT=1e-3)
         w.fluid.replica = r
         if r != 0:
@@ -43,12 +47,13 @@ def _equal(a, b):
     return all(np.array_equal(x, y) for x, y in zip(a, b))
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_graph_replays_match_eager_steps_bitwise(prec):
+@pytest.mark.parametrize("prec,big", [("fp64", False), ("fp32", False), ("fp32", True)])
+def test_graph_replays_match_eager_steps_bitwise(prec, big):
     from paper_1307_0702_amd.ensemble import Ensemble
-    print(f"ensemble graph vs eager, {prec}", flush=True)
-    ref = Ensemble(_members(), prec=prec, tune=False)
-    ens = Ensemble(_members(), prec=prec, tune=False)
+    print(f"ensemble graph vs eager, {prec}, {'per-member chains' if big else 'batched'}",
+          flush=True)
+    ref = Ensemble(_members(big), prec=prec, tune=False)
+    ens = Ensemble(_members(big), prec=prec, tune=False)
     ens.capture(3)
     for rep in range(3):
         ens.run()
