@@ -653,6 +653,8 @@ def run_table1(log_fn):
                          drho_rel_err=r0["amp"] / r0["printed"] - 1,
                          force_x=r1["force"][:, 0].tolist(), gorkov_x=r1["gorkov"].tolist(),
                          ratio=(r1["force"][:, 0] / r1["gorkov"]).tolist(),
+                         gorkov_with_tether_mass_x=r1["gorkov_tether"].tolist(),
+                         ratio_with_tether_mass=(r1["force"][:, 0] / r1["gorkov_tether"]).tolist(),
                          drho_with_particles=r1["amp"])
         log_fn(f"[bench] table I {fig}: drho {r0['amp']:.6e} vs printed {r0['printed']:.6e}; "
                f"F/F_Gorkov {rows[fig]['ratio']}")

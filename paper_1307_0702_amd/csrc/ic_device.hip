@@ -1942,8 +1942,12 @@ __device__ __forceinline__ void cl_stage_body(const StagePassArgs<T> &a, int p) 
     }
 }
 
+// At most 96 VGPRs (5 waves per SIMD, no spills): with its density gather
+// issued beside the momentum loads the pass would otherwise take 100 and
+// drop to 4 waves, which cost more than the shorter chain saves.
 template <typename T>
-__global__ __launch_bounds__(256) void k_cl_stage(const StagePassArgs<T> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_cl_stage(
+    const StagePassArgs<T> a) {
     const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (p >= a.np) return;
     critical_path();

@@ -21,15 +21,26 @@ from . import ic
 from . import workloads as W
 
 
-def _gorkov(fl, amp, me, kappa_ratio, z):
+def _gorkov(fl, amp, me, kappa_ratio, z, m_tether=0.0):
     """Gor'kov's primary force F = c_f^2 amp^2 V k / (4 rho0) (f1 + 3/2 f2)
     sin(2 k z), z measured from the pressure antinode, for the fundamental
-    mode along x."""
+    mode along x.  m_tether: a mass taken off the excess mass in f2 (the
+    tether's reactive mass, see tether_mass)."""
     V = 8.0 * fl.h ** 3
     k = 2.0 * math.pi / (fl.nx * fl.h)
     f1 = 1.0 - kappa_ratio
+    me = me - m_tether
     f2 = 2.0 * me / (2.0 * me + 3.0 * fl.rho0 * V)
     return fl.cf ** 2 * amp * amp * V * k / (4.0 * fl.rho0) * (f1 + 1.5 * f2) * np.sin(2.0 * k * z)
+
+
+def tether_mass(ks, omega):
+    """Reactive mass of a tether at the drive frequency: over one drive
+    period the spring force -k_s (q - q_eq) of a particle oscillating with
+    the wave is k_s/omega^2 times its acceleration, so the particle answers
+    the wave as one with excess mass m_e - k_s/omega^2 (a dipolar term of
+    its own in Gor'kov's f2, whatever the particle's compressibility)."""
+    return ks / omega ** 2
 
 
 def _mode_amplitude_tracker(sim, fl, x0=0.0):
@@ -58,10 +69,14 @@ def _sim(w, prec):
     return sim
 
 
-def table1_run(fig, particles=True, nwarm=40000, nper=10, prec="fp64", log=None):
+def table1_run(fig, particles=True, nwarm=40000, nper=10, prec="fp64", log=None, **kw):
     """Returns dict(amp=measured mode amplitude, printed=Table I's value,
-    force=[2][3] mean -F_tether or None, gorkov=[2] Gor'kov's F_x or None)."""
-    w = W.table1(fig, particles)
+    force=[2][3] mean -F_tether or None, gorkov=[2] Gor'kov's F_x or None,
+    gorkov_tether=[2] the same with the tethers' reactive mass).  kw go to
+    workloads.table1 (n, ks_scale, cp); nwarm is the warm-up for the 32^3
+    box and grows as L^2 with it (the resonant mode's decay time)."""
+    w = W.table1(fig, particles, **kw)
+    nwarm = int(round(nwarm * (w.fluid.nx / 32) ** 2 / w.period_steps)) * w.period_steps
     fl, p = w.fluid, w.particles
     sim = _sim(w, prec)
     if log:
@@ -76,13 +91,16 @@ def table1_run(fig, particles=True, nwarm=40000, nper=10, prec="fp64", log=None)
         sim.step(1)
         add()
     amp = math.sqrt(2.0 * float(acc) / n)
-    out = dict(fig=fig, amp=amp, printed=W.TABLE1[fig]["drho"], force=None, gorkov=None)
+    out = dict(fig=fig, amp=amp, printed=W.TABLE1[fig]["drho"], force=None, gorkov=None,
+               gorkov_tether=None)
     if p.n:
         f, _, _ = sim.avg_force(reset=True)
         L = fl.nx * fl.h
         z = (p.qeq[:, 0] - w.modes[0].x0 + L / 2) % L - L / 2
         out["force"] = f
         out["gorkov"] = _gorkov(fl, amp, p.me[0], p.kappa_ratio[0], z)
+        out["gorkov_tether"] = _gorkov(fl, amp, p.me[0], p.kappa_ratio[0], z,
+                                       tether_mass(p.ks[0], w.modes[0].omega))
     return out
 
 

@@ -263,7 +263,7 @@ TABLE1 = {
 }
 
 
-def table1(fig, particles=True, steps_per_period=320, dp=0.005):
+def table1(fig, particles=True, steps_per_period=320, dp=0.005, n=32, ks_scale=1.0, cp=None):
     """The Table I configuration of figure `fig` ("force" or "force3") in the
     paper's units, with the paper-literal plane drive p_ext = dp sin(omega t)
     on the cells of the plane x = 0 (Sec. VI, Eq. pext; the wave runs along x
@@ -274,22 +274,28 @@ def table1(fig, particles=True, steps_per_period=320, dp=0.005):
     k = 2 pi / L part of the plane drive is 2 (h/L) dp cos(k x)); the other
     modes the plane excites start at rest.  With particles: the symmetric
     pair of Sec. VI at (3L/8, L/2, L/2) and (-3L/8, 0, 0) from the driven
-    plane, m_e and c_p of the figure, on soft tethers (reading R9)."""
+    plane, m_e and c_p of the figure (or `cp`), on soft tethers (reading R9)
+    scaled by ks_scale.  n != 32: the same in an n^3 box, driven at its
+    discrete resonance (2 c_f / h) sin(pi h / L), which is what the printed
+    frequencies are for n = 32 (reading R7)."""
     t = TABLE1[fig]
-    fl = Fluid(32, 32, 32, h=10.0, rho0=1.0, cf=4.0, eta=0.5, zeta=t["zeta"], kT=0.0,
-               dt=2.0 * math.pi / (t["omega"] * steps_per_period), seed=1)
+    omega = t["omega"]
+    if n != 32:
+        omega = discrete_sound_frequency(Fluid(n, n, n, h=10.0, cf=4.0))
+    fl = Fluid(n, n, n, h=10.0, rho0=1.0, cf=4.0, eta=0.5, zeta=t["zeta"], kT=0.0,
+               dt=2.0 * math.pi / (omega * steps_per_period), seed=1)
     L = fl.nx * fl.h
-    mode = Mode(axis=0, shape="plane", m=1, x0=0.0, amp=dp, omega=t["omega"])
+    mode = Mode(axis=0, shape="plane", m=1, x0=0.0, amp=dp, omega=omega)
     nu_l = (4.0 * fl.eta / 3.0 + fl.zeta) / fl.rho0
-    D = 2.0 * (fl.h / L) * dp / (nu_l * t["omega"])
-    drho, g = standing_wave_fields(fl, D, omega=t["omega"])
+    D = 2.0 * (fl.h / L) * dp / (nu_l * omega)
+    drho, g = standing_wave_fields(fl, D, omega=omega)
     V = 8.0 * fl.h ** 3
     if particles:
         qeq = np.array([[3 * L / 8, L / 2, L / 2], [L - 3 * L / 8, 0.0, 0.0]])
         mp = t["me"] + fl.rho0 * V
         p = Particles(q=qeq.copy(), me=np.full(2, t["me"]),
-                      kappa_ratio=np.full(2, (fl.cf / t["cp"]) ** 2),
-                      ks=np.full(2, soft_tether(fl, t["omega"], mp)), qeq=qeq)
+                      kappa_ratio=np.full(2, (fl.cf / (cp or t["cp"])) ** 2),
+                      ks=np.full(2, ks_scale * soft_tether(fl, omega, mp)), qeq=qeq)
     else:
         p = Particles(q=np.zeros((0, 3)), me=np.zeros(0), kappa_ratio=np.zeros(0),
                       ks=np.zeros(0), qeq=np.zeros((0, 3)))

@@ -13,8 +13,16 @@ Eq. pext).  Printed values checked:
   against Gor'kov's F = c_f^2 drho^2 V k / (4 rho0) (f1 + 3/2 f2) sin 2kz
   (Sec. V, Eq. (1)) with the measured amplitude, in the symmetric tethered
   pair of Sec. VI: the paper reports a deviation of 1.5% for the dipolar
-  force and deviations of up to about 10% for the monopolar one at this box
-  size.
+  force and monopolar deviations reaching roughly 10% at this box size.
+
+The tether (reading R9: k_s = m_p (omega/6)^2; the paper prints no spring
+constant) is part of the measurement: at the drive frequency its force on a
+particle oscillating with the wave is k_s/omega^2 times the particle's
+acceleration, so the particle scatters as one with excess mass
+m_e - k_s/omega^2.  Checked: the raw ratios move with k_s by what that
+reactive mass predicts, and with it in Gor'kov's f2 they do not.  With the
+reactive mass counted, the Fig. 3 particle's deficit shrinks as the box
+grows (32^3, 48^3, 64^3 at their discrete resonances), as the paper reports.
 """
 import numpy as np
 import pytest
@@ -64,3 +72,37 @@ def test_table1_monopolar_force_fig3():
     r = f[:, 0] / gork
     assert np.all(np.sign(f[:, 0]) == np.sign(gork))
     assert np.all(np.abs(r - 1) <= 0.12), r
+
+
+def _ratios(fig, **kw):
+    from paper_1307_0702_amd.experiments import table1_run
+    r = table1_run(fig, particles=True, log=lambda m: print(m, flush=True), **kw)
+    raw = float(r["force"][0, 0] / r["gorkov"][0])
+    cor = float(r["force"][0, 0] / r["gorkov_tether"][0])
+    assert np.isclose(r["force"][1, 0], -r["force"][0, 0], rtol=1e-9)
+    print(f"  {fig} {kw}: F/F_Gorkov {raw:.4f}, with the tether's reactive mass {cor:.4f}",
+          flush=True)
+    return raw, cor
+
+
+@pytest.mark.parametrize("fig", ["force3", "force"])
+def test_tether_reactive_mass_accounts_for_the_spring_dependence(fig):
+    # tethers a quarter as stiff as reading R9's, and as stiff
+    raw_soft, cor_soft = _ratios(fig, ks_scale=0.25)
+    raw_r9, cor_r9 = _ratios(fig, ks_scale=1.0)
+    # the spring changes the raw ratio by 2.4% (Fig. 3) and 2.9% (Fig. 4) ...
+    assert abs(raw_soft - raw_r9) > 0.015
+    # ... and Gor'kov's force with m_e - k_s/omega^2 takes all of it
+    assert abs(cor_soft / cor_r9 - 1) < 0.01
+
+
+def test_table1_monopolar_deficit_shrinks_with_the_box():
+    cor = [_ratios("force3", n=n)[1] for n in (32, 48, 64)]
+    d = [1 - c for c in cor]
+    print(f"  Fig. 3 particle, deficit against Gor'kov with the tether's reactive mass: "
+          f"{d[0]:.4f} (32^3), {d[1]:.4f} (48^3), {d[2]:.4f} (64^3)", flush=True)
+    # the paper: a monopolar deviation near 10% at 32h that vanishes as the
+    # box grows
+    assert 0 < d[0] <= 0.10
+    assert d[2] < d[1] < d[0]
+    assert d[2] < 0.75 * d[0]
