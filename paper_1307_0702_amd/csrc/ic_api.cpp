@@ -243,6 +243,11 @@ int ic_create(const ic_params *p, void *stream, ic_ctx **out) {
     c->stream = (hipStream_t)stream;
     c->device = 0;
     (void)hipGetDevice(&c->device);
+    c->ncu = 0;
+    if (hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, c->device) !=
+            hipSuccess ||
+        c->ncu <= 0)
+        c->ncu = 256;
     c->bound = false;
     c->adj_bound = false;
     c->np = 0;

@@ -724,24 +724,25 @@ struct NoiseArgs {
     BMPoly poly;              // FP64 Box-Muller series (unused in FP32)
 };
 
-// Tile of the noise kernel: 32 x NTY<T> columns (32 in FP32, 16 in FP64,
-// whose registers and LDS are twice as wide).  Waves 0-3 also take one side
-// each of the ring of cells whose stresses the tile's faces need (+x column:
-// xx, +y row: yy, -x column: xy and xz, -y row: xy and yz), so each SIMD
-// carries one ring wave.
+// Tile of the noise kernel: 32 x NY columns, NY = NTY<T> (32 in FP32, 16
+// in FP64, whose registers and LDS are twice as wide) when the noise runs on
+// its own, NBG = 8 for the next step's noise run in the background (below).
+// Waves 0-3 also take one side each of the ring of cells whose stresses the
+// tile's faces need (+x column: xx, +y row: yy, -x column: xy and xz, -y row:
+// xy and yz), so each SIMD carries one ring wave (NY >= 8: four waves).
 constexpr int NTX = 32, NPX = NTX + 2;
 template <typename T>
 constexpr int NTY = sizeof(T) == 4 ? 32 : 16;
-template <typename T>
-constexpr int NOISE_THREADS = NTX * NTY<T>;
+constexpr int NBG = 8;
 
 __device__ __forceinline__ int nidx(int lx, int ly) { return (ly + 1) * NPX + (lx + 1); }
 
-// Noise of tile t (of a.gx x a.gy x a.gz tiles); s_S holds the current
-// plane's stresses [W_A, W_B][xx, yy, xy, xz, yz].
-template <typename T>
+// Noise of tile t (of a.gx x a.gy x a.gz tiles of 32 x NY columns); s_S
+// holds the current plane's stresses [W_A, W_B][xx, yy, xy, xz, yz].  The
+// values do not depend on the tile shape.
+template <typename T, int NY>
 __device__ __forceinline__ void noise_body(const NoiseArgs<T> &args, int t,
-                                           T (*s_S)[5][NPX * (NTY<T> + 2)]) {
+                                           T (*s_S)[5][NPX * (NY + 2)]) {
     NoiseArgs<T> a = args;
     const uint32_t m = args.step->cur + args.ahead;
     a.nk.step = m;
@@ -750,8 +751,8 @@ __device__ __forceinline__ void noise_body(const NoiseArgs<T> &args, int t,
     const int plane = nx * ny;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int bx = t % a.gx, by = (t / a.gx) % a.gy, bz = t / (a.gx * a.gy);
-    const int x0 = bx * NTX, y0 = by * NTY<T>, z0 = bz * tz;
-    const int W = min(NTX, nx - x0), Wy = min(NTY<T>, ny - y0), z1 = min(z0 + tz, nz);
+    const int x0 = bx * NTX, y0 = by * NY, z0 = bz * tz;
+    const int W = min(NTX, nx - x0), Wy = min(NY, ny - y0), z1 = min(z0 + tz, nz);
     const int lx = tid % NTX, ly = tid / NTX;
     const bool own = lx < W && ly < Wy;
     const int li = nidx(lx, ly);
@@ -844,19 +845,35 @@ __device__ __forceinline__ void noise_body(const NoiseArgs<T> &args, int t,
 }
 
 template <typename T>
-__global__ __launch_bounds__(NOISE_THREADS<T>) void noise_kernel(const NoiseArgs<T> args) {
+__global__ __launch_bounds__(NTX * NTY<T>) void noise_kernel(const NoiseArgs<T> args) {
     __shared__ T s_S[2][5][NPX * (NTY<T> + 2)];
-    noise_body<T>(args, xcd_tile(blockIdx.x, args.gx * args.gy * args.gz), s_S);
+    noise_body<T, NTY<T>>(args, xcd_tile(blockIdx.x, args.gx * args.gy * args.gz), s_S);
+}
+
+// The next step's noise in the background of the step in flight: one
+// 256-thread block per CU (one wave per SIMD, 56 VGPRs) walks the 32 x 8
+// tiles.  Its waves keep the default issue priority below the stage and
+// particle kernels, so they run in the issue slots those latency-bound
+// kernels leave idle, and a CU gives up one stage block to them instead of
+// two for a 1024-thread tile.  Measured at 256^3 (FP32 ms per step): 1.022
+// with one 32 x 32 tile per block, 0.973 like this; 224 or 288 blocks
+// (some CUs without one or with two) 1.008 and 1.010, 160 blocks 1.18 (the
+// noise then outlasts the step).
+template <typename T>
+__global__ __launch_bounds__(NTX * NBG) void noise_kernel_bg(const NoiseArgs<T> args) {
+    __shared__ T s_S[2][5][NPX * (NBG + 2)];
+    const int nt = args.gx * args.gy * args.gz;
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) noise_body<T, NBG>(args, t, s_S);
 }
 
 // Noise of many contexts in one launch: block b draws tile tile[b] of
 // context member[b].
 template <typename T>
-__global__ __launch_bounds__(NOISE_THREADS<T>) void noise_kernel_batched(
+__global__ __launch_bounds__(NTX * NTY<T>) void noise_kernel_batched(
     const IC_CONST NoiseArgs<T> *args, const IC_CONST int32_t *member,
     const IC_CONST int32_t *tile) {
     __shared__ T s_S[2][5][NPX * (NTY<T> + 2)];
-    noise_body<T>(from_const(args[member[blockIdx.x]]), tile[blockIdx.x], s_S);
+    noise_body<T, NTY<T>>(from_const(args[member[blockIdx.x]]), tile[blockIdx.x], s_S);
 }
 
 // ---------------------------------------------------------------------------
@@ -3220,10 +3237,14 @@ hipError_t step_impl(ic_ctx *c, bool overlap, bool first, bool last) {
     }
     if (noise) {
         NoiseArgs<T> na = noise_args<T>(c);
-        const dim3 ng(na.gx * na.gy * na.gz), nt(NOISE_THREADS<T>);
+        const dim3 ng(na.gx * na.gy * na.gz), nt(NTX * NTY<T>);
         if (ahead) {
-            na.ahead = 1;
-            hipLaunchKernelGGL(noise_kernel<T>, ng, nt, 0, c->side, na);
+            NoiseArgs<T> bg = na;
+            bg.ahead = 1;
+            bg.gy = (p.ny + NBG - 1) / NBG;
+            const int ntile = bg.gx * bg.gy * bg.gz;
+            hipLaunchKernelGGL(noise_kernel_bg<T>, dim3(std::min(ntile, c->ncu)), dim3(NTX * NBG),
+                               0, c->side, bg);
             chk(hipEventRecord(c->ev_noise, c->side));
         }
         if (first) {
@@ -3421,7 +3442,7 @@ template <typename T>
 hipError_t batch_step(const BatchTables<T> &bt, hipStream_t s) {
     hipLaunchKernelGGL(k_step_begin_batched, dim3(bt.n), dim3(64), 0, s, cst(bt.st), cst(bt.drive));
     if (bt.nnoise > 0)
-        hipLaunchKernelGGL(noise_kernel_batched<T>, dim3(bt.nnoise), dim3(NOISE_THREADS<T>), 0, s,
+        hipLaunchKernelGGL(noise_kernel_batched<T>, dim3(bt.nnoise), dim3(NTX * NTY<T>), 0, s,
                            cst(bt.noise), cst(bt.nmember), cst(bt.ntile));
     const WaveMap wm{cst(bt.wmember), cst(bt.wlocal), bt.nwaves};
     if (bt.nwaves > 0) {

@@ -141,6 +141,7 @@ struct ic_ctx {
     ic_params p;
     hipStream_t stream;
     int device;
+    int ncu;   // compute units of the device (one background noise block each)
     bool bound;
     void *f[4];
     ic::Workspace ws;

@@ -272,6 +272,26 @@ def test_bitwise_repeatable():
     assert np.array_equal(a.get_particles()[0], b.get_particles()[0])
 
 
+def test_background_noise_is_bitwise_the_in_line_noise():
+    # FP32 on a grid of >= 2^20 cells: a call of several steps draws each
+    # next step's noise in the background (32 x 8 tiles, one block per CU,
+    # walking the tiles), single-step calls draw it in line (32 x 32 tiles).
+    # Ragged in y for both tile heights, more tiles than CUs.
+    w = W.small_random(nx=130, ny=100, nz=90, npart=40, seed=29, kT=1e-3)
+    a = _sim(w, prec="fp32")
+    for _ in range(3):
+        a.step(1)
+    b = _sim(w, prec="fp32")
+    b.step(3)
+    ra, ga = a.get_state()
+    rb, gb = b.get_state()
+    assert np.array_equal(ra, rb)
+    for c in range(3):
+        assert np.array_equal(ga[c], gb[c])
+    assert np.array_equal(a.get_particles()[0], b.get_particles()[0])
+    assert np.array_equal(a.get_particles()[1], b.get_particles()[1])
+
+
 def test_error_codes_from_device_paths():
     from paper_1307_0702_amd import ic
     w = W.small_random(nx=16, ny=16, nz=16, npart=2, seed=2, kT=0.0)
