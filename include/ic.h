@@ -237,8 +237,13 @@ double ic_eps_from_kappa_ratio(double cf, double kappa_ratio);
 /* Ensembles of independent runs (replicas with their own seeds or replica
  * ids, contrast sweeps, uneven grids and particle counts).
  * ic_graph_create captures nsteps IC steps of each of the n bound contexts
- * into one HIP graph, one dependency chain per context, so that one launch
- * runs the chains concurrently.  The graph holds each context's buffers,
+ * into one HIP graph that one launch replays: a single context of at least
+ * 2^20 cells as its eager schedule (particle prologue and next step's noise
+ * on a second stream beside the stages); contexts of one precision with at
+ * most 512 particles each as one launch per kernel of the step for all of
+ * them; otherwise one chain of single-context launches per context, run
+ * concurrently.  Every form gives each context's eager steps bit for bit.
+ * The graph holds each context's buffers,
  * particle count, forcing and tile extent as they are at capture.  Changing
  * any of them needs a new graph; the step counter and the drive phase live
  * on the device and advance with each replay.  IC_E_STATE if a context is

@@ -861,7 +861,13 @@ int ic_graph_create(ic_ctx *const *ctxs, int32_t n, int64_t nsteps, ic_graph **o
     if (!g) return IC_E_ARG;
     g->ctxs.assign(ctxs, ctxs + n);
     g->nsteps = nsteps;
-    if (batch_supported(ctxs, n)) {
+    // One large grid: capture the eager schedule itself (prologue and next
+    // step's noise on the context's side stream, forked from and joined into
+    // the captured origin stream), which the single-stream batched step
+    // cannot overlap.
+    const ic_params &p0 = ctxs[0]->p;
+    const bool single_large = n == 1 && (double)p0.nx * p0.ny * p0.nz >= 1048576.0;
+    if (!single_large && batch_supported(ctxs, n)) {
         const hipError_t eb = batch_create(ctxs, n, &g->batch);
         if (eb != hipSuccess) {
             delete g;
@@ -888,6 +894,13 @@ int ic_graph_create(ic_ctx *const *ctxs, int32_t n, int64_t nsteps, ic_graph **o
     if (e == hipSuccess && g->batch) {
         // batched: each kernel of a step once for every context
         for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) e = batch_step(g->batch, origin);
+    } else if (e == hipSuccess && single_large) {
+        ic_ctx *c = ctxs[0];
+        const hipStream_t own = c->stream;
+        c->stream = origin;
+        for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s)
+            e = launch_step(c, true, s == 0, s == nsteps - 1);
+        c->stream = own;
     } else if (e == hipSuccess) {
         e = hipEventRecord(fork, origin);
         for (int32_t i = 0; i < n && e == hipSuccess; ++i) {

@@ -72,6 +72,27 @@ def test_graph_replays_match_eager_steps_bitwise(prec, big):
     ens.release()
 
 
+def test_graph_of_one_large_grid_matches_eager_steps_bitwise():
+    # >= 2^20 cells: the graph holds the eager two-stream schedule (prologue
+    # and next step's noise beside the stages)
+    from paper_1307_0702_amd import ic
+    from paper_1307_0702_amd.ensemble import Ensemble
+    print("graph of one 130 x 100 x 90 grid vs eager, fp32", flush=True)
+    w = W.small_random(nx=130, ny=100, nz=90, npart=40, seed=31, kT=1e-3)
+    ref = Ensemble([w], prec="fp32", tune=False)
+    ens = Ensemble([W.small_random(nx=130, ny=100, nz=90, npart=40, seed=31, kT=1e-3)],
+                   prec="fp32", tune=False)
+    ens.capture(4)
+    for rep in range(3):
+        ens.run()
+        got = _snapshot(ens.sims[0])
+        ref.run_serial(4)
+        want = _snapshot(ref.sims[0])
+        assert _equal(got, want), rep
+    assert ic.ic_get_step(ens.sims[0].ctx) == 12
+    ens.release()
+
+
 def _close(a, b, tol):
     worst = 0.0
     for x, y in zip(a, b):
