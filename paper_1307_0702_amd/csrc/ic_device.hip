@@ -2594,8 +2594,12 @@ __global__ __launch_bounds__(256) void k_adj_rho(const AdjArgs<T> a) {
     cell_of(j, a.nx, a.ny, x, y, z);
     const int jm[3] = {j + (x == 0 ? a.nx - 1 : -1), j + (y == 0 ? a.nx * (a.ny - 1) : -a.nx),
                        j + (z == 0 ? a.nx * a.ny * (a.nz - 1) : -a.nx * a.ny)};
-    const T mu = a.mur[j] + (T)0.5 * ((a.murf[0][jm[0]] + a.murf[1][jm[1]]) + a.murf[2][jm[2]]);
-    adj_combine(a, 0, j, a.lam[0][j], mu);
+    // every value here is read once: non-temporal, like the stores
+    const T mu = __builtin_nontemporal_load(&a.mur[j]) +
+                 (T)0.5 * ((__builtin_nontemporal_load(&a.murf[0][jm[0]]) +
+                            __builtin_nontemporal_load(&a.murf[1][jm[1]])) +
+                           __builtin_nontemporal_load(&a.murf[2][jm[2]]));
+    adj_combine(a, 0, j, __builtin_nontemporal_load(&a.lam[0][j]), mu);
 }
 
 // ---------------------------------------------------------------------------
