@@ -232,6 +232,62 @@ struct ic_graph {
 
 extern "C" {
 
+// ic_step's graph: RUN_STEPS steps, each taking its noise from the step
+// before and drawing the next one's, captured from the eager schedule on a
+// private stream and replayed on the context stream.  Everything the
+// captured launches bake in is in the signature; a change recaptures.
+static const int64_t RUN_STEPS = 16;
+
+static std::vector<char> run_signature(const ic_ctx *c) {
+    std::vector<char> s;
+    auto put = [&s](const void *p, size_t n) {
+        s.insert(s.end(), (const char *)p, (const char *)p + n);
+    };
+    put(&c->np, sizeof c->np);
+    put(&c->tz, sizeof c->tz);
+    put(c->nblk, sizeof c->nblk);
+    put(c->f, sizeof c->f);
+    put(&c->ws, sizeof c->ws);
+    put(&c->side, sizeof c->side);
+    put(&c->forcing.nmodes, sizeof c->forcing.nmodes);
+    put(c->forcing.modes, sizeof(ic_mode) * (size_t)c->forcing.nmodes);
+    return s;
+}
+
+static void drop_run_graph(ic_ctx *c) {
+    if (c->run_exec) (void)hipGraphExecDestroy(c->run_exec);
+    if (c->run_graph) (void)hipGraphDestroy(c->run_graph);
+    c->run_exec = nullptr;
+    c->run_graph = nullptr;
+    c->run_sig.clear();
+}
+
+static hipError_t capture_run_graph(ic_ctx *c) {
+    drop_run_graph(c);
+    hipStream_t origin = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&origin, hipStreamNonBlocking);
+    bool capturing = false;
+    if (e == hipSuccess) {
+        e = hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal);
+        capturing = e == hipSuccess;
+    }
+    const hipStream_t own = c->stream;
+    c->stream = origin;
+    for (int64_t s = 0; s < RUN_STEPS && e == hipSuccess; ++s) e = launch_step(c, true, false, false);
+    c->stream = own;
+    if (capturing) {
+        const hipError_t e2 = hipStreamEndCapture(origin, &c->run_graph);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->run_exec, c->run_graph, nullptr, nullptr, 0);
+    if (origin) (void)hipStreamDestroy(origin);
+    if (e == hipSuccess)
+        c->run_sig = run_signature(c);
+    else
+        drop_run_graph(c);
+    return e;
+}
+
 int ic_create(const ic_params *p, void *stream, ic_ctx **out) {
     if (!out) return IC_E_ARG;
     *out = nullptr;
@@ -266,12 +322,17 @@ int ic_create(const ic_params *p, void *stream, ic_ctx **out) {
     c->prof_launches = 0;
     c->side = nullptr;
     c->ev_fork = c->ev_part = c->ev_noise = nullptr;
+    c->run_graph = nullptr;
+    c->run_exec = nullptr;
+    c->noise_ready = -1;
     *out = c;
     return IC_OK;
 }
 
 int ic_destroy(ic_ctx *c) {
     if (!c) return IC_OK;
+    if (c->run_exec) (void)hipStreamSynchronize(c->stream);
+    drop_run_graph(c);
     if (!c->ev_pending.empty()) (void)hipStreamSynchronize(c->stream);
     for (auto &pr : c->ev_pending) {
         (void)hipEventDestroy(pr.first);
@@ -361,6 +422,7 @@ int ic_bind(ic_ctx *c, void *drho, void *gx, void *gy, void *gz, void *workspace
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "bind");
     c->bound = true;
+    c->noise_ready = -1;
     return IC_OK;
 }
 
@@ -472,6 +534,7 @@ int ic_set_step(ic_ctx *c, int64_t n) {
     if (!c) return IC_E_ARG;
     if (n < 0) return fail(c, IC_E_ARG, "step must be >= 0");
     c->step = n;
+    c->noise_ready = -1;
     if (c->bound) {
         hipError_t e = launch_set_step(c);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -505,13 +568,42 @@ int ic_step(ic_ctx *c, int64_t nsteps) {
     if (rc != IC_OK) return rc;
     if (nsteps < 0) return fail(c, IC_E_ARG, "nsteps < 0");
     // The side stream pays for its event round trips only on large grids;
-    // small grids are launch-latency-bound and step on one stream.
+    // small grids are launch-latency-bound and step on one stream, drawing
+    // each step's noise in line.  On large grids a step draws the next one's
+    // noise in the background, except FP64 steps launched one by one (beside
+    // FP64 stages launched from the host the FP64 noise kernel cost more
+    // than it hid; inside the graph it hides).
     const bool overlap = (double)c->p.nx * c->p.ny * c->p.nz >= 1048576.0;
-    for (int64_t s = 0; s < nsteps; ++s) {
-        hipError_t e = launch_step(c, overlap, s == 0, s == nsteps - 1);
-        if (e != hipSuccess) return hip_fail(c, e, "step launch");
+    const bool noise = c->p.kT > 0.0;
+    const bool eager_ahead = c->p.prec != IC_FP64;
+    hipError_t e = hipSuccess;
+    auto one = [&](bool ahead) {
+        const bool first = !(noise && c->noise_ready == c->step);
+        e = launch_step(c, overlap, first, !ahead);
+        if (e != hipSuccess) return;
         c->step += 1;
         if (c->np > 0) c->nsamples += 1;
+        c->noise_ready = noise && overlap && ahead ? c->step : -1;
+    };
+    int64_t s = 0;
+    if (overlap && !c->profiling && nsteps >= RUN_STEPS + 1) {
+        if (noise && c->noise_ready != c->step) {
+            one(true);
+            ++s;
+        }
+        if (e == hipSuccess && (!c->run_exec || c->run_sig != run_signature(c))) e = capture_run_graph(c);
+        for (; e == hipSuccess && s + RUN_STEPS <= nsteps; s += RUN_STEPS) {
+            e = hipGraphLaunch(c->run_exec, c->stream);
+            if (e != hipSuccess) break;
+            c->step += RUN_STEPS;
+            if (c->np > 0) c->nsamples += RUN_STEPS;
+            c->noise_ready = noise ? c->step : -1;
+        }
+        if (e != hipSuccess) return hip_fail(c, e, "step graph");
+    }
+    for (; s < nsteps; ++s) {
+        one(eager_ahead);
+        if (e != hipSuccess) return hip_fail(c, e, "step launch");
     }
     return IC_OK;
 }
@@ -946,6 +1038,7 @@ int ic_graph_launch(ic_graph *g, void *stream) {
     for (ic_ctx *c : g->ctxs) {
         c->step += g->nsteps;
         if (c->np > 0) c->nsamples += g->nsteps;
+        c->noise_ready = -1;   // the graph's steps reuse the noise sets
     }
     return IC_OK;
 }

@@ -3227,10 +3227,9 @@ hipError_t step_impl(ic_ctx *c, bool overlap, bool first, bool last) {
     const unsigned nblk_all = (unsigned)(c->nblk[0] * c->nblk[1] * c->nblk[2]);
     const int np = c->np;
     const bool noise = p.kT > 0.0;
-    // Next-step noise beside the stages in FP32 only: the FP64 noise kernel
-    // is FP64-ALU-bound for about 1.5 stage sweeps and, run concurrently,
-    // slowed the stage kernels by more than it hid (measured at 256^3).
-    if (!overlap || sizeof(T) == 8) first = last = true;
+    // first: draw this step's noise in line; !last: draw the next step's in
+    // the background of this one.  One stream draws in line only.
+    if (!overlap) first = last = true;
     const bool ahead = noise && !last;
     const bool side_part = overlap && np > 0;
     const hipStream_t ps = side_part ? c->side : s;   // stream of the particle prologue

@@ -166,6 +166,13 @@ struct ic_ctx {
     // reverse mode (ic_bind_adjoint)
     bool adj_bound;
     ic::AdjWorkspace adj;
+    // ic_step's own graph of a few steps (grids of >= 2^20 cells), replayed
+    // while the launch arguments it captured (run_sig) still hold
+    hipGraph_t run_graph;
+    hipGraphExec_t run_exec;
+    std::vector<char> run_sig;
+    // step whose noise increments the previous step already drew (-1: none)
+    int64_t noise_ready;
 };
 
 namespace ic {

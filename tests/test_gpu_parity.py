@@ -272,24 +272,71 @@ def test_bitwise_repeatable():
     assert np.array_equal(a.get_particles()[0], b.get_particles()[0])
 
 
-def test_background_noise_is_bitwise_the_in_line_noise():
-    # FP32 on a grid of >= 2^20 cells: a call of several steps draws each
-    # next step's noise in the background (32 x 8 tiles, one block per CU,
-    # walking the tiles), single-step calls draw it in line (32 x 32 tiles).
-    # Ragged in y for both tile heights, more tiles than CUs.
-    w = W.small_random(nx=130, ny=100, nz=90, npart=40, seed=29, kT=1e-3)
-    a = _sim(w, prec="fp32")
-    for _ in range(3):
-        a.step(1)
-    b = _sim(w, prec="fp32")
-    b.step(3)
+def _same(a, b):
     ra, ga = a.get_state()
     rb, gb = b.get_state()
     assert np.array_equal(ra, rb)
     for c in range(3):
         assert np.array_equal(ga[c], gb[c])
-    assert np.array_equal(a.get_particles()[0], b.get_particles()[0])
-    assert np.array_equal(a.get_particles()[1], b.get_particles()[1])
+    qa, ua = a.get_particles()
+    qb, ub = b.get_particles()
+    assert np.array_equal(qa, qb) and np.array_equal(ua, ub)
+    assert a.conserved().tolist() == b.conserved().tolist()
+
+
+def _large(seed=29):
+    # >= 2^20 cells (two streams, background noise, step graphs), ragged in
+    # y for the 32 x 32 and 32 x 8 noise tiles, more tiles than CUs
+    return W.small_random(nx=130, ny=100, nz=90, npart=40, seed=seed, kT=1e-3)
+
+
+def test_background_noise_is_bitwise_the_in_line_noise():
+    # b draws every step's noise in line (setting the step counter forgets
+    # any noise drawn ahead), a draws each next step's in the background
+    from paper_1307_0702_amd import ic
+    w = _large()
+    a = _sim(w, prec="fp32")
+    a.step(3)
+    b = _sim(w, prec="fp32")
+    for n in range(3):
+        ic.ic_set_step(b.ctx, n)
+        b.step(1)
+    _same(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_step_graph_is_bitwise_the_launched_steps(prec):
+    # 45 steps in one call: one launched step, two replays of the 16-step
+    # graph, 12 launched steps; against 45 calls of one step
+    from paper_1307_0702_amd import ic
+    w = _large(seed=37)
+    a = _sim(w, prec=prec)
+    a.step(45)
+    b = _sim(w, prec=prec)
+    for _ in range(45):
+        b.step(1)
+    _same(a, b)
+    assert ic.ic_get_step(a.ctx) == 45
+    # a changed forcing is recaptured, the particle count too
+    modes = modes_of(w)
+    modes[0]["amp"] *= 2.0
+    for sim in (a, b):
+        sim.set_forcing(modes)
+    a.step(20)
+    for _ in range(20):
+        b.step(1)
+    _same(a, b)
+    p = w.particles
+    from paper_1307_0702_amd import ic as _ic
+    eps = np.array([_ic.ic_eps_from_kappa_ratio(w.fluid.cf, r) for r in p.kappa_ratio])
+    for sim in (a, b):
+        q, u = sim.get_particles()
+        sim.set_particles(q[:30], p.me[:30], eps[:30], u=u[:30], ks=p.ks[:30], qeq=p.qeq[:30],
+                          fext=p.fext[:30])
+    a.step(17)
+    for _ in range(17):
+        b.step(1)
+    _same(a, b)
 
 
 def test_error_codes_from_device_paths():
