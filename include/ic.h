@@ -147,12 +147,16 @@ int ic_get_tile(ic_ctx *ctx, int32_t *tz);
 /* Advances the bound state by nsteps IC time steps (App. A, "Temporal
  * discretization", substeps 1-7, with the three SSP-RK3 stages of the fluid
  * update).  Asynchronous.  On grids of 2^20 cells or more, part of each step
- * (the particle prologue and, in FP32, the next step's noise) runs on a
- * second stream owned by the context, which every step joins back into the
- * context stream before it ends, so ordering against the caller's work on
- * that stream is unchanged.  A step whose no-slip impulse finds
- * m_e + m_f <= 0 raises a device flag reported by the next synchronising
- * call as IC_E_MASS. */
+ * (the particle prologue and the next step's noise) runs on a second stream
+ * owned by the context, which every step joins back into the context stream
+ * before it ends, so ordering against the caller's work on that stream is
+ * unchanged; a call of 17 steps or more replays a 16-step HIP graph of the
+ * same launches, captured on first use and again whenever the particle
+ * count, forcing, tile extent or bound buffers have changed (not while
+ * ic_profile is on).  Noise drawn ahead by the last step of a call serves
+ * the next call, unless ic_set_step, ic_bind or an ic_graph_launch comes in
+ * between.  A step whose no-slip impulse finds m_e + m_f <= 0 raises a
+ * device flag reported by the next synchronising call as IC_E_MASS. */
 int ic_step(ic_ctx *ctx, int64_t nsteps);
 
 /* Averaging operator J (Sec. II, Eq. Jdis; staggered positions of App. A):
@@ -222,9 +226,9 @@ int ic_avg_force(ic_ctx *ctx, double *f_out, double *lambda_out, int64_t *nsampl
  * sum h^3 g + sum_p m_e u_p (Sec. IV C, total momentum).  Synchronising. */
 int ic_conserved(ic_ctx *ctx, double out[4]);
 
-/* Instrumentation.  With enable != 0, ic_step brackets every fluid-stage
- * kernel launch (the three RK sweeps of App. A) with HIP events on the
- * context stream.  ic_profile_read synchronises, returns the summed duration
+/* Instrumentation.  With enable != 0, ic_step launches every step one by
+ * one and brackets every fluid-stage kernel launch (the three RK sweeps of
+ * App. A) with HIP events on the context stream.  ic_profile_read synchronises, returns the summed duration
  * of those kernels in ms and their number of launches since the last read,
  * and clears both. */
 int ic_profile(ic_ctx *ctx, int32_t enable);
