@@ -591,8 +591,10 @@ int ic_step(ic_ctx *c, int64_t nsteps) {
             one(true);
             ++s;
         }
-        if (e == hipSuccess && (!c->run_exec || c->run_sig != run_signature(c))) e = capture_run_graph(c);
-        for (; e == hipSuccess && s + RUN_STEPS <= nsteps; s += RUN_STEPS) {
+        if (e == hipSuccess && (!c->run_exec || c->run_sig != run_signature(c)) &&
+            capture_run_graph(c) != hipSuccess)
+            (void)hipGetLastError();   // no graph: the steps below are launched one by one
+        for (; e == hipSuccess && c->run_exec && s + RUN_STEPS <= nsteps; s += RUN_STEPS) {
             e = hipGraphLaunch(c->run_exec, c->stream);
             if (e != hipSuccess) break;
             c->step += RUN_STEPS;

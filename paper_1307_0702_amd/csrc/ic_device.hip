@@ -18,7 +18,10 @@
 // step, call, replica), and each stage reads its combination.  The particle
 // terms run as one wave per cluster of particles whose kernels may touch the
 // same points, members in ascending id.  There are no float atomics in the
-// forward step, so its results are bitwise reproducible.
+// forward step, so its results are bitwise reproducible.  Data a sweep
+// touches once streams past L2 (non-temporal), which keeps L2 for the halo
+// the neighbouring blocks re-read; the next step's noise is drawn in the
+// background of the step in flight by one block per CU.
 #include <math.h>
 
 #include <algorithm>

@@ -67,3 +67,12 @@ def test_faxen_radius_of_the_kernel():
         r = (r + 5) % 10 - 5
         rf.append(math.sqrt(3 * np.sum(w[0] * r * r)))
     assert abs(np.mean(rf) - val) <= tol * val
+
+
+def test_table1_printed_amplitudes_are_the_workload_values():
+    # the GPU test of Table I reads these; the workload builder carries the
+    # same numbers
+    from paper_1307_0702_amd import workloads as W
+    g = _golden()
+    for fig in ("force", "force3"):
+        assert g["table1_drho_" + fig][0] == W.TABLE1[fig]["drho"]
