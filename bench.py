@@ -87,7 +87,7 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_gpu(w, prec, steps, warmup, graph=True):
+def run_gpu(w, prec, steps, warmup, graph=True, one_by_one=False):
     import torch
 
     from paper_1307_0702_amd import ic
@@ -101,14 +101,21 @@ def run_gpu(w, prec, steps, warmup, graph=True):
         sim.set_particles(p.q, p.me, eps, ks=p.ks, qeq=p.qeq, fext=p.fext)
     if w.modes:
         sim.set_forcing([m.as_dict() for m in w.modes])
+    if one_by_one:
+        # every step launched one by one (ic_profile keeps ic_step off its
+        # graph), so a kernel trace holds only the schedule of the profiled pass
+        ic.ic_profile(sim.ctx, 1)
     log(f"[bench] {prec}: warmup {warmup} steps")
     sim.step(warmup)
+    # the step graph that an ic_step call of 5 steps or more replays is
+    # captured here, not inside the timed call (no step is run)
+    sim.prepare()
     sim.synchronize()
     stream = sim.stream
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     # the timed steps: one ic_step call, as a user makes it (on grids of
-    # >= 2^20 cells it replays its 16-step graph and launches the rest)
+    # >= 2^20 cells it replays its 4-step graph and launches the rest)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
@@ -823,6 +830,9 @@ def main():
                     help="skip the reverse-mode step cost in the default line")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the graph-replayed step (a kernel trace then holds only the timed launches)")
+    ap.add_argument("--one-by-one", action="store_true",
+                    help="launch the warm-up and timed steps one by one too, as the profiled pass "
+                         "is (for kernel traces; ms_per_step is then that schedule's)")
     ap.add_argument("--no-force-precision", action="store_true",
                     help="skip the FP32-against-FP64 averaged-force leg of the default line")
     ap.add_argument("--force-steps", type=int, default=20000,
@@ -893,7 +903,8 @@ def main():
     res = {}
     precs = ["fp32", "fp64"] if args.prec == "both" else [args.prec]
     for prec in precs:
-        res[prec] = run_gpu(w, prec, args.steps, args.warmup, graph=not args.no_graph)
+        res[prec] = run_gpu(w, prec, args.steps, args.warmup, graph=not args.no_graph,
+                            one_by_one=args.one_by_one)
     main_prec = precs[0]
     r = res[main_prec]
     out = dict(
@@ -915,6 +926,8 @@ def main():
         graph_ms_per_step=r["graph_ms_per_step"],
         roofline=roofline(r, main_prec),
     )
+    if args.one_by_one:
+        out["schedule"] = "every step launched one by one"
     if not args.no_adjoint:
         # the reverse-mode cost of the metric: one reversed step with
         # particles against one forward step (adjoint-64 workload)

@@ -150,7 +150,7 @@ int ic_get_tile(ic_ctx *ctx, int32_t *tz);
  * (the particle prologue and the next step's noise) runs on a second stream
  * owned by the context, which every step joins back into the context stream
  * before it ends, so ordering against the caller's work on that stream is
- * unchanged; a call of 17 steps or more replays a 16-step HIP graph of the
+ * unchanged; a call of 5 steps or more replays a 4-step HIP graph of the
  * same launches, captured on first use and again whenever the particle
  * count, forcing, tile extent or bound buffers have changed (not while
  * ic_profile is on).  Noise drawn ahead by the last step of a call serves
@@ -158,6 +158,16 @@ int ic_get_tile(ic_ctx *ctx, int32_t *tz);
  * between.  A step whose no-slip impulse finds m_e + m_f <= 0 raises a
  * device flag reported by the next synchronising call as IC_E_MASS. */
 int ic_step(ic_ctx *ctx, int64_t nsteps);
+
+/* Captures now the 4-step graph that ic_step replays on grids of 2^20 cells
+ * or more (for the current particle count, forcing, tile extent and bound
+ * buffers), so that the first ic_step call of 5 steps or more does not pay
+ * for the capture.  Runs no step and changes no state.  IC_OK also when no
+ * graph applies (a smaller grid, ic_profile on) or the capture fails (ic_step
+ * then tries again, and launches its steps one by one if it fails there
+ * too); IC_E_ARG / IC_E_STATE as ic_step for a missing or unbound context.
+ * Not during an ic_step of the context on another host thread. */
+int ic_step_prepare(ic_ctx *ctx);
 
 /* Averaging operator J (Sec. II, Eq. Jdis; staggered positions of App. A):
  * out[p] = sum_i h^3 theta_h(q_p - r_i) field[i] for n positions q ([n][3])

@@ -236,7 +236,7 @@ extern "C" {
 // before and drawing the next one's, captured from the eager schedule on a
 // private stream and replayed on the context stream.  Everything the
 // captured launches bake in is in the signature; a change recaptures.
-static const int64_t RUN_STEPS = 16;
+static const int64_t RUN_STEPS = 4;
 
 static std::vector<char> run_signature(const ic_ctx *c) {
     std::vector<char> s;
@@ -607,6 +607,16 @@ int ic_step(ic_ctx *c, int64_t nsteps) {
         one(eager_ahead);
         if (e != hipSuccess) return hip_fail(c, e, "step launch");
     }
+    return IC_OK;
+}
+
+int ic_step_prepare(ic_ctx *c) {
+    const int rc = check_bound(c);
+    if (rc != IC_OK) return rc;
+    const bool overlap = (double)c->p.nx * c->p.ny * c->p.nz >= 1048576.0;
+    if (!overlap || c->profiling || (c->run_exec && c->run_sig == run_signature(c))) return IC_OK;
+    if (capture_run_graph(c) != hipSuccess)
+        (void)hipGetLastError();   // ic_step captures again, or launches one by one
     return IC_OK;
 }
 

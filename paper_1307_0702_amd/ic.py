@@ -26,6 +26,7 @@ IC_NOALLOC_MAX_POINTS = 16384
 EXPORTED = [
     "ic_create", "ic_destroy", "ic_workspace_size", "ic_bind", "ic_set_particles",
     "ic_get_particles", "ic_set_forcing", "ic_set_step", "ic_get_step", "ic_step",
+    "ic_step_prepare",
     "ic_interpolate", "ic_interpolate_noalloc", "ic_spread", "ic_avg_force", "ic_conserved",
     "ic_eps_from_kappa_ratio", "ic_strerror", "ic_last_error", "ic_profile", "ic_profile_read",
     "ic_set_tile", "ic_get_tile", "ic_graph_create", "ic_graph_launch", "ic_graph_destroy",
@@ -75,6 +76,7 @@ def load_library(path=LIB_PATH):
         "ic_set_step": ([P, ctypes.c_int64], ctypes.c_int),
         "ic_get_step": ([P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "ic_step": ([P, ctypes.c_int64], ctypes.c_int),
+        "ic_step_prepare": ([P], ctypes.c_int),
         "ic_interpolate": ([P, ctypes.c_int32, P, ctypes.c_int32, P, P], ctypes.c_int),
         "ic_interpolate_noalloc": ([P, ctypes.c_int32, P, ctypes.c_int32, P, P], ctypes.c_int),
         "ic_spread": ([P, ctypes.c_int32, P, P, ctypes.c_int32, P], ctypes.c_int),
@@ -185,6 +187,10 @@ def ic_get_step(ctx):
 
 def ic_step(ctx, nsteps):
     _check(_lib.ic_step(ctx, int(nsteps)), ctx)
+
+
+def ic_step_prepare(ctx):
+    _check(_lib.ic_step_prepare(ctx), ctx)
 
 
 def ic_set_tile(ctx, tz):
@@ -388,6 +394,10 @@ class Simulation:
 
     def step(self, n=1):
         ic_step(self.ctx, n)
+
+    def prepare(self):
+        """Captures the step graph of long ic_step calls now (ic_step_prepare)."""
+        ic_step_prepare(self.ctx)
 
     def set_tile(self, tz):
         ic_set_tile(self.ctx, tz)

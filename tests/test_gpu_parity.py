@@ -306,17 +306,18 @@ def test_background_noise_is_bitwise_the_in_line_noise():
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_step_graph_is_bitwise_the_launched_steps(prec):
-    # 45 steps in one call: one launched step, two replays of the 16-step
-    # graph, 12 launched steps; against 45 calls of one step
+    # 46 steps in one call: one launched step (the first step's noise is not
+    # drawn ahead), 11 replays of the 4-step graph, one launched step;
+    # against 46 calls of one step
     from paper_1307_0702_amd import ic
     w = _large(seed=37)
     a = _sim(w, prec=prec)
-    a.step(45)
+    a.step(46)
     b = _sim(w, prec=prec)
-    for _ in range(45):
+    for _ in range(46):
         b.step(1)
     _same(a, b)
-    assert ic.ic_get_step(a.ctx) == 45
+    assert ic.ic_get_step(a.ctx) == 46
     # a changed forcing is recaptured, the particle count too
     modes = modes_of(w)
     modes[0]["amp"] *= 2.0
@@ -337,6 +338,31 @@ def test_step_graph_is_bitwise_the_launched_steps(prec):
     for _ in range(17):
         b.step(1)
     _same(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_prepared_step_graph_is_bitwise_the_launched_steps(prec):
+    # 3 steps (too few for the graph), the graph captured without running a
+    # step, then 21 steps in one call (five replays of the 4-step graph and
+    # one launched step); against 24 calls of one step
+    from paper_1307_0702_amd import ic
+    w = _large(seed=41)
+    a = _sim(w, prec=prec)
+    a.step(3)
+    a.prepare()
+    assert ic.ic_get_step(a.ctx) == 3
+    a.prepare()   # nothing changed: the graph is kept
+    a.step(21)
+    b = _sim(w, prec=prec)
+    for _ in range(24):
+        b.step(1)
+    _same(a, b)
+    # a grid too small for the graph, and a profiled context: nothing to do
+    s = _sim(W.small_random(nx=16, ny=12, nz=14, npart=2, seed=3, kT=1e-3), prec=prec)
+    s.prepare()
+    ic.ic_profile(a.ctx, 1)
+    a.prepare()
+    ic.ic_profile(a.ctx, 0)
 
 
 def test_error_codes_from_device_paths():
