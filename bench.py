@@ -105,11 +105,12 @@ def run_gpu(w, prec, steps, warmup, graph=True, one_by_one=False):
         # every step launched one by one (ic_profile keeps ic_step off its
         # graph), so a kernel trace holds only the schedule of the profiled pass
         ic.ic_profile(sim.ctx, 1)
+    # the step graph that an ic_step call of 5 steps or more replays is
+    # captured here (no step is run), not inside the timed call; the warm-up
+    # then follows without a pause
+    sim.prepare()
     log(f"[bench] {prec}: warmup {warmup} steps")
     sim.step(warmup)
-    # the step graph that an ic_step call of 5 steps or more replays is
-    # captured here, not inside the timed call (no step is run)
-    sim.prepare()
     sim.synchronize()
     stream = sim.stream
     e0 = torch.cuda.Event(enable_timing=True)
