@@ -355,13 +355,17 @@ class Simulation:
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
-        if ctx is not None:
-            try:
-                self.synchronize()
-            except Exception:
-                pass
-            _lib.ic_destroy(ctx)
-            self.ctx = None
+        # at interpreter shutdown the module's globals may already be gone;
+        # the process is ending then, and its device memory goes with it
+        lib = globals().get("_lib")
+        if ctx is None or lib is None:
+            return
+        try:
+            self.synchronize()
+        except Exception:
+            pass
+        lib.ic_destroy(ctx)
+        self.ctx = None
 
     def synchronize(self):
         self.stream.synchronize()
