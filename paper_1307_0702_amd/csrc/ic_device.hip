@@ -2259,6 +2259,21 @@ __global__ __launch_bounds__(256) void k_cl_post(const PostPassArgs<T> c) {
     cl_post_body(c, p);
 }
 
+// The last stage's particle terms and substeps 4-7 in one launch: a
+// cluster's points are written by its own wave alone, so its substeps 4-7
+// can follow its stage terms without waiting for the other clusters (the
+// same operations in the same order as k_cl_stage then k_cl_post).
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_cl_last(
+    const StagePassArgs<T> a, const PostPassArgs<T> c) {
+    const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (p >= a.np) return;
+    critical_path();
+    cl_stage_body(a, p);
+    member_fence();
+    cl_post_body(c, p);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_cl_noslip(const PostPassArgs<T> c) {
     const int p = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -3294,12 +3309,14 @@ hipError_t step_impl(ic_ctx *c, bool overlap, bool first, bool last) {
         }
         if (np > 0) {
             if (st == 0 && side_part) chk(hipStreamWaitEvent(s, c->ev_part, 0));
-            hipLaunchKernelGGL(k_cl_stage<T>, dim3(wave_blocks(np)), dim3(256), 0, s,
-                               stage_pass_args<T>(c, st));
+            if (st < 2)
+                hipLaunchKernelGGL(k_cl_stage<T>, dim3(wave_blocks(np)), dim3(256), 0, s,
+                                   stage_pass_args<T>(c, st));
+            else
+                hipLaunchKernelGGL(k_cl_last<T>, dim3(wave_blocks(np)), dim3(256), 0, s,
+                                   stage_pass_args<T>(c, st), post_args<T>(c));
         }
     }
-    if (np > 0)
-        hipLaunchKernelGGL(k_cl_post<T>, dim3(wave_blocks(np)), dim3(256), 0, s, post_args<T>(c));
     if (ahead) chk(hipStreamWaitEvent(s, c->ev_noise, 0));
     chk(hipGetLastError());
     return err;
