@@ -83,6 +83,7 @@ def test_unbound_and_null_contexts_are_refused_before_device_work():
     i64 = ctypes.c_int64()
     calls = {
         "ic_step": lambda c: L.ic_step(c, 1),
+        "ic_step_prepare": lambda c: L.ic_step_prepare(c),
         "ic_set_particles": lambda c: L.ic_set_particles(c, 1, buf, None, buf, buf, None, None, None),
         "ic_get_particles": lambda c: L.ic_get_particles(c, buf, buf),
         "ic_get_state": lambda c: L.ic_get_state(c, None, None, None, None, buf, buf),
