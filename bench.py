@@ -749,6 +749,44 @@ def stats_summary(path):
                                        r["Percentage"]))
 
 
+def timeline_summary(path, first_step, nsteps):
+    """Median schedule of one step from a rocprofv3 kernel trace of this
+    script: every kernel's start and end relative to the start of the step's
+    first stage sweep, over the timed steps of the first run in the trace
+    (steps first_step .. first_step + nsteps - 2 of that precision, i.e. after
+    the warm-up and before the profiled pass)."""
+    ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), _short(r["Kernel_Name"]))
+                for r in csv.DictReader(open(path)))
+    first = [i for i, x in enumerate(ev) if x[2].startswith("stage_kernel<") and ", 0," in x[2]]
+    prec = ev[first[0]][2].split("<")[1].split(",")[0]
+    first = [i for i in first if ev[i][2].startswith("stage_kernel<" + prec + ",")]
+    rows = {}
+    steps = range(first_step, min(first_step + nsteps, len(first)) - 1)
+    for j in steps:
+        t0, t1 = ev[first[j]][0], ev[first[j + 1]][0]
+        seen = {}
+        for s, e, name in ev:
+            # the step: from its k_step_begin (just before the sweep) up to the
+            # next step's
+            if t0 - 20000 <= s < t1 - 20000:
+                k = (name, seen.get(name, 0))
+                seen[name] = k[1] + 1
+                rows.setdefault(k, []).append(((s - t0) / 1e3, (e - t0) / 1e3))
+    print(f"# {prec}, median over {len(steps)} steps; us from the start of the first sweep")
+    print("%-48s %9s %9s %9s" % ("kernel", "start_us", "end_us", "dur_us"))
+    out = []
+    for (name, n), v in rows.items():
+        if len(v) < len(steps) // 2:
+            continue
+        st = float(np.median([a for a, _ in v]))
+        en = float(np.median([b for _, b in v]))
+        out.append((st, en, name))
+    for st, en, name in sorted(out):
+        print("%-48s %9.1f %9.1f %9.1f" % (name[:48], st, en, en - st))
+    nxt = float(np.median([(ev[first[j + 1]][0] - ev[first[j]][0]) / 1e3 for j in steps]))
+    print("%-48s %9.1f" % ("next step's first sweep", nxt))
+
+
 def _pmc(dirname):
     per = {}
     for fn in os.listdir(dirname):
@@ -840,6 +878,9 @@ def main():
                     help="steps of each run of the averaged-force precision leg")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--stats-summary", metavar="CSV")
+    ap.add_argument("--timeline-summary", metavar="TRACE_CSV",
+                    help="median schedule of one step from a rocprofv3 kernel trace of this "
+                         "script (give the run's --steps and --warmup)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"))
     ap.add_argument("--instr-summary", metavar="DIR")
     args = ap.parse_args()
@@ -847,6 +888,8 @@ def main():
         return instr_summary(args.instr_summary)
     if args.stats_summary:
         return stats_summary(args.stats_summary)
+    if args.timeline_summary:
+        return timeline_summary(args.timeline_summary, args.warmup, args.steps)
     if args.pmc_summary:
         return pmc_summary(*args.pmc_summary)
     if args.gpus != 1:
