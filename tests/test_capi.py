@@ -14,6 +14,21 @@ def _declared():
     return sorted(set(re.findall(r"\b(ic_[a-z_]+)\s*\(", txt)))
 
 
+def test_header_is_plain_c(tmp_path):
+    # the boundary header compiles as C99 (no C++ types in any signature)
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use_ic.c"
+    src.write_text('#include "ic.h"\nint main(void) { return 0; }\n')
+    res = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                          "-fsyntax-only", "-I" + os.path.join(ROOT, "include"), str(src)],
+                         capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr
+
+
 def test_header_and_binding_agree():
     from paper_1307_0702_amd import ic
     assert _declared() == sorted(ic.EXPORTED)
