@@ -2289,6 +2289,19 @@ __global__ __launch_bounds__(256) void k_cl_post_batched(const IC_CONST PostPass
     cl_post_body(from_const(args[map.member[w]]), map.local[w]);
 }
 
+// k_cl_last for every member of an ensemble in one launch.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cl_last_batched(
+    const IC_CONST StagePassArgs<T> *sargs, const IC_CONST PostPassArgs<T> *pargs,
+    const WaveMap map) {
+    const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (w >= map.nwaves) return;
+    const int m = map.member[w], p = map.local[w];
+    cl_stage_body(from_const(sargs[m]), p);
+    member_fence();
+    cl_post_body(from_const(pargs[m]), p);
+}
+
 // ---------------------------------------------------------------------------
 // Adjoint (reverse mode) of one deterministic, particle-free RK3 step: the
 // transpose of the stage increment Delta(U) (conservative staggered flux of
@@ -3494,13 +3507,13 @@ hipError_t batch_step(const BatchTables<T> &bt, hipStream_t s) {
         else
             hipLaunchKernelGGL((stage_kernel_batched<T, 2>), g, b, 0, s, cst(bt.stage[2]),
                                cst(bt.tmember), cst(bt.ttile));
-        if (bt.nwaves > 0)
+        if (bt.nwaves > 0 && st < 2)
             hipLaunchKernelGGL(k_cl_stage_batched<T>, dim3(wave_blocks(bt.nwaves)), dim3(256), 0, s,
                                cst(bt.pass[st]), wm);
+        else if (bt.nwaves > 0)
+            hipLaunchKernelGGL(k_cl_last_batched<T>, dim3(wave_blocks(bt.nwaves)), dim3(256), 0, s,
+                               cst(bt.pass[2]), cst(bt.post), wm);
     }
-    if (bt.nwaves > 0)
-        hipLaunchKernelGGL(k_cl_post_batched<T>, dim3(wave_blocks(bt.nwaves)), dim3(256), 0, s,
-                           cst(bt.post), wm);
     return hipGetLastError();
 }
 
