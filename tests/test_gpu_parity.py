@@ -132,6 +132,22 @@ def test_fp64_particles_on_periodic_seams():
     _run_both(w, 3)
 
 
+@pytest.mark.parametrize("centre", [(20.0, 18.0, 16.0), (0.0, 0.0, 0.0)])
+def test_fp64_dense_cluster_matches_oracle(centre):
+    # 600 particles packed in a cube of 6 h (in the middle of the box, or
+    # across the periodic corner): more particles than the one-workgroup
+    # clustering takes, tile lists longer than the union buffer (merged
+    # whole), and a cluster of hundreds of members that one wave applies
+    # member after member; overlapping kernels throughout (Jacobi reading)
+    w = W.small_random(nx=40, ny=36, nz=32, npart=600, seed=21, kT=1e-3)
+    rng = np.random.default_rng(5)
+    p, fl = w.particles, w.fluid
+    L = np.array([fl.nx, fl.ny, fl.nz]) * fl.h
+    p.q[:] = (np.array(centre) * fl.h + rng.uniform(-3.0, 3.0, size=p.q.shape) * fl.h) % L
+    p.qeq[:] = p.q
+    _run_both(w, 2, check_every=1)
+
+
 def test_fp64_initial_velocity_from_no_slip():
     w = W.small_random(nx=20, ny=16, nz=12, npart=4, seed=3, kT=0.0, min_sep=3.5)
     w.particles.u = None
