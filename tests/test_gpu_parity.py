@@ -321,6 +321,22 @@ def test_background_noise_is_bitwise_the_in_line_noise():
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_particle_free_step_graph_is_bitwise_the_in_line_noise(prec):
+    # no particles: the side stream carries only the next step's noise; 21
+    # steps in one call (graph replays) against 21 steps each drawing its
+    # noise in line
+    from paper_1307_0702_amd import ic
+    w = W.small_random(nx=130, ny=100, nz=90, npart=0, seed=43, kT=1e-3)
+    a = _sim(w, prec=prec)
+    a.step(21)
+    b = _sim(w, prec=prec)
+    for n in range(21):
+        ic.ic_set_step(b.ctx, n)
+        b.step(1)
+    _same(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_step_graph_is_bitwise_the_launched_steps(prec):
     # 46 steps in one call: one launched step (the first step's noise is not
     # drawn ahead), 11 replays of the 4-step graph, one launched step;
