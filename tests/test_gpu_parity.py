@@ -148,6 +148,18 @@ def test_fp64_dense_cluster_matches_oracle(centre):
     _run_both(w, 2, check_every=1)
 
 
+def test_fp32_dense_cluster_one_step():
+    # the same pack in FP32 storage (fields start from FP32 values)
+    w = W.small_random(nx=40, ny=36, nz=32, npart=600, seed=23, kT=1e-3)
+    rng = np.random.default_rng(6)
+    p, fl = w.particles, w.fluid
+    p.q[:] = np.array([20.0, 18.0, 16.0]) * fl.h + rng.uniform(-3.0, 3.0, size=p.q.shape) * fl.h
+    p.qeq[:] = p.q
+    w.drho = w.drho.astype(np.float32).astype(np.float64)
+    w.g = w.g.astype(np.float32).astype(np.float64)
+    _run_both(w, 1, prec="fp32", tol=1e-5)
+
+
 def test_fp64_initial_velocity_from_no_slip():
     w = W.small_random(nx=20, ny=16, nz=12, npart=4, seed=3, kT=0.0, min_sep=3.5)
     w.particles.u = None
