@@ -123,6 +123,13 @@ def test_fp64_grid_smaller_than_tile():
     _run_both(w, 3)
 
 
+def test_fp64_smallest_grid():
+    # 4 cells per side, the smallest grid accepted: a particle's influence
+    # box wraps onto itself on every axis, so all particles form one cluster
+    w = W.small_random(nx=4, ny=4, nz=4, npart=3, seed=9, kT=1e-3)
+    _run_both(w, 3, check_every=1)
+
+
 def test_fp64_particles_on_periodic_seams():
     w = W.small_random(nx=36, ny=12, nz=34, npart=6, seed=13, kT=1e-3)
     L = np.array([36.0, 12.0, 34.0])
