@@ -1,6 +1,7 @@
 """Host-side logic that needs no GPU: the default stage-tile extent, the
 workspace layouts (two noise sets, the adjoint workspace), the benchmark's
-refusal of more than one GPU and its traffic bookkeeping."""
+refusal of more than one GPU, its traffic bookkeeping and its kernel-trace
+timeline summary."""
 import os
 import subprocess
 import sys
@@ -88,3 +89,39 @@ def test_bench_traffic_only_for_the_profiled_source(monkeypatch):
     monkeypatch.setattr(bench, "kernel_source_sha", lambda: "0" * 64)
     t2, note2 = bench.measured_traffic("fp32")
     assert t2 is None and "changed" in note2
+
+
+def test_timeline_summary_of_a_synthetic_trace(tmp_path, capsys):
+    # two precisions' worth of steps in one trace: the summary takes the
+    # first run's steps after the warm-up, offsets from each step's first
+    # sweep, medians over the steps
+    sys.path.insert(0, ROOT)
+    import bench
+    rows = []
+
+    def add(name, s, e):
+        rows.append(dict(Kernel_Name=name, Start_Timestamp=str(int(s * 1000)),
+                         End_Timestamp=str(int(e * 1000))))
+
+    sweep0 = "void ic::(anonymous namespace)::stage_kernel<float, 0, true, true>(ic::(anonymous namespace)::StageArgs<float>)"
+    sweep1 = "void ic::(anonymous namespace)::stage_kernel<float, 1, true, true>(ic::(anonymous namespace)::StageArgs<float>)"
+    for n in range(6):          # 2 warm-up + 4 timed steps of 1000 us, the sweeps at +0 and +400
+        t = 1000.0 * n + (3.0 if n == 3 else 0.0)
+        add("void ic::(anonymous namespace)::k_step_begin(ic::StepState*, DriveArgs)", t - 10, t - 8)
+        add(sweep0, t, t + 300)
+        add(sweep1, t + 400, t + 700)
+    for n in range(2):          # a second precision afterwards is not counted
+        t = 10000.0 + 1000.0 * n
+        add(sweep0.replace("float", "double"), t, t + 900)
+    path = tmp_path / "trace.csv"
+    with open(path, "w") as f:
+        f.write("Kernel_Name,Start_Timestamp,End_Timestamp\n")
+        for r in rows:
+            f.write('"%s",%s,%s\n' % (r["Kernel_Name"], r["Start_Timestamp"], r["End_Timestamp"]))
+    bench.timeline_summary(str(path), 2, 4)
+    out = capsys.readouterr().out.splitlines()
+    assert out[0].startswith("# float, median over 3 steps")
+    body = {l[:48].strip(): l[48:].split() for l in out[2:]}
+    assert [float(x) for x in body["stage_kernel<float, 0, true, true>"]] == [0.0, 300.0, 300.0]
+    assert [float(x) for x in body["stage_kernel<float, 1, true, true>"]] == [400.0, 700.0, 300.0]
+    assert float(body["next step's first sweep"][0]) == 1000.0
