@@ -22,16 +22,19 @@ def _gpu():
 
 def _members(big=False):
     # uneven grids and particle counts, own seeds and replica ids; one member
-    # driven, one without particles.  big: the second member holds 600
-    # particles, above the 512 that one workgroup clusters, so the graph
-    # holds one chain of single-context launches per member instead of the
-    # batched kernels.
+    # with a cosine drive, one with a plane drive (along y), one without
+    # particles.  big: the second member holds 600 particles, above the 512
+    # that one workgroup clusters, so the graph holds one chain of
+    # single-context launches per member instead of the batched kernels.
     ws = []
     shapes = [(36, 20, 24, 7), (48, 40, 40, 600) if big else (32, 32, 16, 3), (20, 18, 22, 0)]
     for r, (nx, ny, nz, npart) in enumerate(shapes):
         w = W.small_random(nx=nx, ny=ny, nz=nz, npart=npart, seed=50 + r, kT=1e-3)
         w.fluid.replica = r
-        if r != 0:
+        if r == 1:
+            w.modes = [W.Mode(axis=1, shape="plane", m=1, x0=3.0 * w.fluid.h, amp=2e-3,
+                              omega=w.modes[0].omega if w.modes else 0.1)]
+        elif r != 0:
             w.modes = []
         ws.append(w)
     return ws
