@@ -537,7 +537,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &a, int t, T *lds)
         // ---- phase B: velocities of plane k+1, fluxes of plane k
         T vn[3] = {0, 0, 0}, vn1[3] = {0, 0, 0};
         T un[4] = {0, 0, 0, 0}, nn[3] = {0, 0, 0}, mflux = 0, Pxz = 0, Pyz = 0;
-        if (!PREP && own) {
+        // FP64: the pointwise loads go out after the barrier, just before
+        // their use, so they are not held across the flux phase
+        constexpr bool EARLY = sizeof(T) == 4;
+        if (EARLY && !PREP && own) {
             const uint32_t su = soff(zk);
             if (STAGE != 0) {
 #pragma unroll
@@ -615,6 +618,17 @@ __device__ __forceinline__ void stage_body(const StageArgs<T> &a, int t, T *lds)
         // above), then plane k+1 into G/V and density of plane k+2 into P
         if (own) {
             if (!PREP) {
+                if (!EARLY) {
+                    const uint32_t su = soff(zk);
+                    if (STAGE != 0) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) un[c] = bload<T, CP_NT>(run[c], vo, su);
+                    }
+                    if (NOISE) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) nn[c] = bload<T, CP_NT>(rnn[c], vo, su);
+                    }
+                }
                 const int l = lo;
                 // own column of plane k: only this thread writes it below
                 const T us[4] = {Pk[l], s_G[0][l], s_G[1][l], s_G[2][l]};
